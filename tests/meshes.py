@@ -1,0 +1,30 @@
+"""Tiny hand-built meshes for the oracle pins (inputs only, no method arithmetic)."""
+import numpy as np
+
+
+def single_tet(scale=1e-6):
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float) * scale
+    return dict(verts=verts, tets=np.array([[0, 1, 2, 3]], np.int32), region=None)
+
+
+def mirror_pair(scale=1e-6):
+    """Two tets mirror-imaged through their shared face z = 0."""
+    verts = np.array([[0, 0, 0], [1, 0, 0], [0.3, 0.9, 0], [0.4, 0.3, 0.8], [0.4, 0.3, -0.8]],
+                     float) * scale
+    tets = np.array([[0, 1, 2, 3], [0, 1, 2, 4]], np.int32)
+    return dict(verts=verts, tets=tets, region=None)
+
+
+def model(D, reactions, species, n_regions=1):
+    S, R = len(species), len(reactions)
+    idx = {s: i for i, s in enumerate(species)}
+    lhs = np.zeros((R, S), np.int32)
+    rhs = np.zeros((R, S), np.int32)
+    k = np.zeros((n_regions, max(R, 1)))[:, :R]
+    for r, (l, rr, kv) in enumerate(reactions):
+        for s in l:
+            lhs[r, idx[s]] += 1
+        for s in rr:
+            rhs[r, idx[s]] += 1
+        k[:, r] = kv
+    return dict(D=np.asarray(D, float), lhs=lhs, rhs=rhs, kcst=k)
