@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the operator-splitting reaction-diffusion hot path on one GPU.
+
+A step is one complete simulated run of the simple-model workload: a 10 x 10 x
+100 um box of 0.5 um cubes (480,000 jittered tets), 10 species / 12 reactions,
+1e6 molecules, 100 ms simulated = 220 windows (219 of tau, one truncated), every
+window doing the reaction SSA and the diffusion update of every tet.  The
+initial counts are resident in HBM before timing; each step resets the
+simulation to them (device-to-device) and runs to t_end.
+
+Prints one JSON line: voxel-steps/s (the value), SSA events/s and molecules
+moved/s, the roofline of the window kernel (algorithmic bytes per launch over
+its average launch time from HIP events on the launch stream), and the oracle
+timed on host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes(T: int, S: int, n_regions: int, molecules_moved: int) -> float:
+    """Bytes one window must move: counts read + written (8 S per tet), the
+    neighbour ids (16), the couplings G, c0, c1, c2 (32), N_A V (8), the region
+    label when the model has regions (1), and one 4-byte read-modify-write per
+    moved molecule's target count (8 each; moved molecules bound the nonzero
+    face moves from above)."""
+    per_tet = 8 * S + 16 + 32 + 8 + (1 if n_regions > 1 else 0)
+    return float(T) * per_tet + 8.0 * molecules_moved
+
+
+def cpu_baseline(workload, seconds: float = 12.0) -> dict:
+    """The oracle, single-threaded, on the same mesh/model/seed/counts for as
+    many whole windows as fit in about `seconds`."""
+    from oracle import oracle as O
+
+    inst = O.Instance(workload.mesh.as_dict(), workload.model.as_dict(), workload.seed)
+    inst.reset(workload.counts)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds:
+        inst.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": inst.tallies.voxel_steps / dt, "unit": "voxel-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {n} windows of the same run ({n * inst.T} voxel-steps, "
+                      f"{inst.tallies.ssa_events} SSA events) in {dt:.1f} s on one host core",
+            "ssa_events_per_s": inst.tallies.ssa_events / dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the workload is a single simulation on one "
+              "device (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    rdx.lib()  # fails loudly if the HIP library is missing
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    w = inputs.config_simple()
+    t0 = time.perf_counter()
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    setup_s = time.perf_counter() - t0
+    T, S = sim.T, sim.S
+    n_regions = w.model.kcst.shape[0]
+    counts0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        sim.set_counts(counts0, stream=stream)
+        sim.run(w.t_end, stream=stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    st0 = sim.stats(stream)
+    windows_per_step = st0.windows
+
+    # timed region: K steps; HIP events on the launch stream bracket the window
+    # launches of every step (the count reset before them is outside the pair)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    events_total = 0
+    moves_total = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        sim.set_counts(counts0, stream=stream)
+        ev[k][0].record(stream)
+        sim.run(w.t_end, stream=stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    # tallies of the last step (each step restarts from the same counts)
+    st = sim.stats(stream)
+    events_total = st.ssa_events * args.steps
+    moves_total = st.moves * args.steps
+    kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
+    launches = windows_per_step * args.steps
+    avg_launch_s = kernel_ms * 1e-3 / launches
+    voxel_steps = T * windows_per_step * args.steps
+    bytes_per_launch = algorithmic_bytes(T, S, n_regions, st.moves / windows_per_step)
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+
+    out = {
+        "metric": "voxel-steps/s & SSA events/s at 1 GPU; batched p50/p99 latency vs plain",
+        "value": voxel_steps / elapsed,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+i32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_tets": T, "species": S, "reactions": sim.R,
+                   "molecules": int(w.counts.sum()), "t_end_s": w.t_end,
+                   "windows_per_step": windows_per_step, "tau_s": sim.tau,
+                   "parallelism": "single GPU"},
+        "ssa_events_per_s": events_total / elapsed,
+        "moves_per_s": moves_total / elapsed,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "window_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    sim.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,183 @@
+/*
+ * rdx.h -- C ABI of the MI355X (gfx950) operator-splitting stochastic
+ * reaction-diffusion library.
+ *
+ * The method is the one of "Parallel STEPS" (Chen & De Schutter,
+ * arXiv:1610.02258): the run from t to t_end is cut into windows of constant
+ * length tau (section 2.1); in each window every tetrahedron runs an exact SSA
+ * over its own reactions, tracking species occupancy, and then every
+ * diffusive species leaves each tet in a binomial number that is split among
+ * the face neighbours in proportion to the face diffusion rates (section 2.2,
+ * Algorithm 1).  On one GPU the paper's remote change buffers become direct
+ * neighbour updates through the tet adjacency.
+ *
+ * Conventions shared by every entry point
+ *   - Counts are int32, laid out species-major: counts[s * n_tets + tet].
+ *   - Time is in seconds (FP64); lengths in metres; diffusion coefficients in
+ *     m^2/s; rate constants in SI molar units: order 0 in M/s, order 1 in 1/s,
+ *     order 2 in 1/(M s).  The mesoscopic constant of a reaction in a tet of
+ *     volume V is k (N_A V[L])^(1 - order); a homodimer 2A uses N(N-1)/2 pairs.
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed; counter =
+ *     (draw call, stream, tet, window), stream 0 = the tet's SSA, stream 1+s =
+ *     diffusion of species s.  Results depend only on (instance, seed, initial
+ *     counts, window sequence), not on launch shapes or on other simulations
+ *     sharing the GPU.
+ *   - Every function returns an rdx_status; on failure rdx_last_error()
+ *     returns a message for the calling thread.  Nothing is thrown across the
+ *     ABI.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Host pointers
+ *     are read or written before the call returns; device pointers
+ *     (is_device_ptr != 0) are accessed in stream order and must stay valid
+ *     until the stream reaches the call.
+ *   - Input arrays are owned by the caller and copied; device state is owned
+ *     by the library and released by rdx_destroy.
+ */
+#ifndef RDX_H
+#define RDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RDX_OK = 0,
+  RDX_EINVAL = -1,      /* bad argument (null pointer, size out of range, bad table) */
+  RDX_EMESH = -2,       /* non-positive tet volume, or a face shared by more than two tets */
+  RDX_ENODIFF = -3,     /* no diffusive species and no tau override: tau undefined */
+  RDX_ENOMEM = -4,      /* host or device allocation failed */
+  RDX_EOVERFLOW = -5,   /* a molecule count passed 2^30 */
+  RDX_EHIP = -6,        /* a HIP runtime call failed */
+  RDX_EBUDGET = -7,     /* request larger than the server's device-memory budget */
+  RDX_ECANCELLED = -8,  /* request cancelled */
+  RDX_EEVENTS = -9,     /* more than 2^22 SSA events in one tet in one window */
+  RDX_ESTATE = -10      /* call not valid in the object's current state */
+} rdx_status;
+
+/* Tetrahedral mesh.  verts [n_verts*3] (x, y, z per vertex, metres);
+ * tets [n_tets*4] vertex indices; region [n_tets] region label per tet (< the
+ * model's n_regions) or NULL for all zero.  Face k of a tet is the face
+ * opposite its local vertex k. */
+typedef struct rdx_mesh {
+  int32_t n_verts;
+  int32_t n_tets;
+  const double* verts;
+  const int32_t* tets;
+  const uint8_t* region;
+} rdx_mesh;
+
+/* Reaction-diffusion model (section 2.1: the per-tet SSA system and the
+ * diffusions it hosts).  diff_coef [n_species] (0 = immobile);
+ * lhs, rhs [n_reactions*n_species] stoichiometry (reaction order = row sum of
+ * lhs, at most 2); kcst [n_regions*n_reactions] rate constant of each reaction
+ * in each mesh region.  Limits: 1 <= n_species <= 16, 0 <= n_reactions <= 32,
+ * 1 <= n_regions <= 8; a reaction changes at most 8 species. */
+typedef struct rdx_model {
+  int32_t n_species;
+  int32_t n_reactions;
+  int32_t n_regions;
+  const double* diff_coef;
+  const int32_t* lhs;
+  const int32_t* rhs;
+  const double* kcst;
+} rdx_model;
+
+/* Cumulative tallies since the last rdx_set_counts: windows run, voxel-steps
+ * (tets x windows), applied SSA events, molecules moved between tets. */
+typedef struct rdx_stats {
+  int64_t windows;
+  int64_t voxel_steps;
+  int64_t ssa_events;
+  int64_t moves;
+  double t;
+  int64_t window_index;
+} rdx_stats;
+
+typedef struct rdx_sim rdx_sim;
+
+/* Set-up (section 2.1): builds the face adjacency, the face couplings
+ * g_k = A_k / (V h_k) (A shared-face area, h barycentre distance), the window
+ * tau = min over (species, tet) of 1/(D_S sum_k g_k) -- or tau_override when
+ * > 0 -- and uploads the instance to the current HIP device.  seed keys all
+ * random streams.  *out receives a handle with zero counts at t = 0.
+ * Errors: RDX_EINVAL, RDX_EMESH, RDX_ENODIFF, RDX_ENOMEM, RDX_EHIP. */
+rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t seed,
+                      double tau_override, rdx_sim** out);
+
+/* Releases all host and device memory of the simulation (NULL is ignored). */
+void rdx_destroy(rdx_sim* sim);
+
+/* Initial populations (section 2.1, last step): counts [n_species*n_tets].
+ * Resets t, the window index and the tallies to zero.
+ * Errors: RDX_EINVAL (null, negative or > 2^30 entries), RDX_EHIP. */
+rdx_status rdx_set_counts(rdx_sim* sim, const int32_t* counts, int is_device_ptr, void* stream);
+
+/* Current counts into out [n_species*n_tets] (host or device pointer). */
+rdx_status rdx_get_counts(rdx_sim* sim, int32_t* out, int is_device_ptr, void* stream);
+
+/* Runtime main loop (Algorithm 1): windows of tau from the current t to t_end,
+ * the last one truncated to t_end - t (after it t = t_end exactly).  Enqueued
+ * on `stream`; does not synchronise.  t_end <= t is a no-op.
+ * Errors: RDX_EINVAL, RDX_EHIP; device-side RDX_EOVERFLOW / RDX_EEVENTS are
+ * reported by the next rdx_get_stats or rdx_sync. */
+rdx_status rdx_run(rdx_sim* sim, double t_end, void* stream);
+
+/* n_windows full windows of length tau (t advances by tau each). */
+rdx_status rdx_step(rdx_sim* sim, int64_t n_windows, void* stream);
+
+/* Waits for the simulation's work on `stream`, then reports any device-side
+ * error flag (RDX_EOVERFLOW, RDX_EEVENTS). */
+rdx_status rdx_sync(rdx_sim* sim, void* stream);
+
+/* Synchronises `stream` and returns the tallies, t and window index. */
+rdx_status rdx_get_stats(rdx_sim* sim, rdx_stats* stats, void* stream);
+
+rdx_status rdx_get_tau(const rdx_sim* sim, double* tau);
+rdx_status rdx_get_sizes(const rdx_sim* sim, int32_t* n_tets, int32_t* n_species,
+                         int32_t* n_reactions);
+
+/* Derived set-up arrays, host pointers, each may be NULL: nbr [n_tets*4]
+ * (-1 = boundary), g [n_tets*4], G [n_tets] (sum of g), csplit [n_tets*4]
+ * (g_k / (g_k + ... + g_3), 0 on boundary faces), nav [n_tets] (N_A V[L]). */
+rdx_status rdx_get_geometry(const rdx_sim* sim, int32_t* nbr, double* g, double* G,
+                            double* csplit, double* nav);
+
+/* The same set-up arrays and tau computed on the host only, without creating
+ * a simulation or touching a GPU (same layouts as rdx_get_geometry; *tau
+ * receives the window).  Errors as rdx_create except RDX_ENOMEM/RDX_EHIP. */
+rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, double tau_override,
+                              int32_t* nbr, double* g, double* G, double* csplit, double* nav,
+                              double* tau);
+
+/* Checkpoint: counts, t, window index and tallies.  With buf == NULL, *len
+ * receives the required size.  Resume is bit-identical because every draw is
+ * addressed by the window index. */
+rdx_status rdx_save(rdx_sim* sim, void* buf, size_t* len, void* stream);
+rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* rdx_last_error(void);
+
+/* ABI version of this header (major * 100 + minor). */
+int32_t rdx_version(void);
+
+/* ---- device self-tests of the random layer (host pointers, synchronous) ---- */
+
+/* Philox4x32-10 on the device: in [n*6] = (ctr0..3, key0, key1), out [n*4]. */
+rdx_status rdx_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n);
+
+/* The library's basic-operation natural logarithm on the device, x > 0 normal. */
+rdx_status rdx_selftest_ln(const double* x, double* y, int64_t n);
+
+/* n binomial variates Bin(m, p); sample j is drawn from the species stream
+ * (seed, stream_id, tet = j, window), exactly as the diffusion step draws. */
+rdx_status rdx_selftest_binom(uint64_t seed, uint32_t stream_id, uint32_t window, int64_t m,
+                              double p, int64_t n, int64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RDX_H */

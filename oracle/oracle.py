@@ -146,9 +146,13 @@ class Instance:
         self.lhs = np.ascontiguousarray(model["lhs"], np.int32).reshape(-1, self.S)
         self.rhs = np.ascontiguousarray(model["rhs"], np.int32).reshape(-1, self.S)
         self.R = int(self.lhs.shape[0])
-        self.kcst = np.ascontiguousarray(model["kcst"], np.float64).reshape(-1, self.R) \
-            if self.R else np.zeros((1, 0))
-        self.n_regions = int(self.kcst.shape[0]) if self.R else int(model.get("n_regions", 1))
+        kc = np.ascontiguousarray(model["kcst"], np.float64)
+        if self.R:
+            self.kcst = kc.reshape(-1, self.R)
+            self.n_regions = int(self.kcst.shape[0])
+        else:
+            self.n_regions = int(kc.shape[0]) if kc.ndim == 2 else int(model.get("n_regions", 1))
+            self.kcst = np.zeros((self.n_regions, 0))
         self.T = int(self.tets.shape[0])
         self.seed = int(seed)
         h = C.c_void_p()

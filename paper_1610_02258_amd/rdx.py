@@ -1,0 +1,267 @@
+"""Thin ctypes binding of the C ABI in ``include/rdx.h`` (``librdx.so``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  NumPy arrays are passed as host pointers; torch tensors on a
+GPU are passed as device pointers together with torch's current stream.
+Importing this module never falls back to anything: if ``librdx.so`` is
+missing, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librdx.so")
+
+STATUS = {0: "RDX_OK", -1: "RDX_EINVAL", -2: "RDX_EMESH", -3: "RDX_ENODIFF", -4: "RDX_ENOMEM",
+          -5: "RDX_EOVERFLOW", -6: "RDX_EHIP", -7: "RDX_EBUDGET", -8: "RDX_ECANCELLED",
+          -9: "RDX_EEVENTS", -10: "RDX_ESTATE"}
+
+# Every function the header declares, with its ctypes signature.
+_p = C.c_void_p
+SIGNATURES = {
+    "rdx_create": ([_p, _p, C.c_uint64, C.c_double, C.POINTER(C.c_void_p)], C.c_int),
+    "rdx_destroy": ([_p], None),
+    "rdx_set_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_get_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_run": ([_p, C.c_double, _p], C.c_int),
+    "rdx_step": ([_p, C.c_int64, _p], C.c_int),
+    "rdx_sync": ([_p, _p], C.c_int),
+    "rdx_get_stats": ([_p, _p, _p], C.c_int),
+    "rdx_get_tau": ([_p, C.POINTER(C.c_double)], C.c_int),
+    "rdx_get_sizes": ([_p, _p, _p, _p], C.c_int),
+    "rdx_get_geometry": ([_p, _p, _p, _p, _p, _p], C.c_int),
+    "rdx_setup_geometry": ([_p, _p, C.c_double, _p, _p, _p, _p, _p, C.POINTER(C.c_double)], C.c_int),
+    "rdx_save": ([_p, _p, C.POINTER(C.c_size_t), _p], C.c_int),
+    "rdx_load": ([_p, _p, C.c_size_t, _p], C.c_int),
+    "rdx_last_error": ([], C.c_char_p),
+    "rdx_version": ([], C.c_int32),
+    "rdx_selftest_philox": ([_p, _p, C.c_int64], C.c_int),
+    "rdx_selftest_ln": ([_p, _p, C.c_int64], C.c_int),
+    "rdx_selftest_binom": ([C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_double, C.c_int64,
+                            _p], C.c_int),
+}
+
+
+class RdxError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Loads librdx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1610_02258_amd.build` (needs hipcc)")
+        # PyTorch-ROCm ships its own HIP and HSA runtimes; loading torch first
+        # makes librdx.so bind to those (same sonames), so that the library, torch
+        # tensors and torch streams share one runtime in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise RdxError(status, where, lib().rdx_last_error().decode(errors="replace"))
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_tets", C.c_int32), ("verts", _p), ("tets", _p),
+                ("region", _p)]
+
+
+class _Model(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32), ("n_regions", C.c_int32),
+                ("diff_coef", _p), ("lhs", _p), ("rhs", _p), ("kcst", _p)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("windows", C.c_int64), ("voxel_steps", C.c_int64), ("ssa_events", C.c_int64),
+                ("moves", C.c_int64), ("t", C.c_double), ("window_index", C.c_int64)]
+
+
+@dataclass
+class Stats:
+    windows: int
+    voxel_steps: int
+    ssa_events: int
+    moves: int
+    t: float
+    window_index: int
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _stream_ptr(stream):
+    """hipStream_t from None (default stream), an int, or a torch stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _is_torch_cuda(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+def _marshal(mesh: dict, model: dict):
+    verts = np.ascontiguousarray(mesh["verts"], np.float64)
+    tets = np.ascontiguousarray(mesh["tets"], np.int32)
+    region = mesh.get("region")
+    region = None if region is None else np.ascontiguousarray(region, np.uint8)
+    D = np.ascontiguousarray(model["D"], np.float64)
+    S = D.shape[0]
+    lhs = np.ascontiguousarray(model["lhs"], np.int32).reshape(-1, S)
+    rhs = np.ascontiguousarray(model["rhs"], np.int32).reshape(-1, S)
+    R = lhs.shape[0]
+    kcst = np.ascontiguousarray(model["kcst"], np.float64)
+    if R:
+        kcst = kcst.reshape(-1, R)
+        n_regions = kcst.shape[0]
+    else:
+        n_regions = kcst.shape[0] if kcst.ndim == 2 else int(model.get("n_regions", 1))
+        kcst = np.zeros((n_regions, 0))
+    m = _Mesh(verts.shape[0], tets.shape[0], _np_ptr(verts), _np_ptr(tets), _np_ptr(region))
+    md = _Model(S, R, n_regions, _np_ptr(D), _np_ptr(lhs), _np_ptr(rhs), _np_ptr(kcst))
+    keep = (verts, tets, region, D, lhs, rhs, kcst)
+    return m, md, keep, int(tets.shape[0]), int(S), int(R)
+
+
+def setup_geometry(mesh: dict, model: dict, tau_override: float = 0.0) -> dict:
+    """Host-only set-up arrays (adjacency, couplings, tau); no GPU needed."""
+    m, md, keep, T, S, R = _marshal(mesh, model)
+    out = dict(nbr=np.zeros((T, 4), np.int32), g=np.zeros((T, 4)), G=np.zeros(T),
+               csplit=np.zeros((T, 4)), nav=np.zeros(T))
+    tau = C.c_double()
+    _check(lib().rdx_setup_geometry(C.byref(m), C.byref(md), float(tau_override),
+                                    *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "csplit", "nav")],
+                                    C.byref(tau)), "rdx_setup_geometry")
+    out["tau"] = tau.value
+    return out
+
+
+class Sim:
+    """One simulation: mesh + model + seed, device-resident counts.
+
+    mesh: dict(verts [V,3] float64 m, tets [T,4] int32, region [T] uint8 | None)
+    model: dict(D [S], lhs [R,S], rhs [R,S], kcst [n_regions,R])
+    """
+
+    def __init__(self, mesh: dict, model: dict, seed: int, tau_override: float = 0.0):
+        L = lib()
+        m, md, keep, T, S, R = _marshal(mesh, model)
+        h = C.c_void_p()
+        _check(L.rdx_create(C.byref(m), C.byref(md), int(seed) & (2**64 - 1), float(tau_override),
+                            C.byref(h)), "rdx_create")
+        self._h = h
+        self.T, self.S, self.R = T, S, R
+        tau = C.c_double()
+        _check(L.rdx_get_tau(h, C.byref(tau)), "rdx_get_tau")
+        self.tau = tau.value
+        self.seed = int(seed)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rdx_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state ---------------------------------------------------------------
+    def set_counts(self, counts, stream=None):
+        if _is_torch_cuda(counts):
+            assert counts.dtype.itemsize == 4 and counts.is_contiguous() and counts.numel() == self.S * self.T
+            _check(lib().rdx_set_counts(self._h, counts.data_ptr(), 1, _stream_ptr(stream)),
+                   "rdx_set_counts")
+        else:
+            c = np.ascontiguousarray(counts, np.int32).reshape(self.S, self.T)
+            _check(lib().rdx_set_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_set_counts")
+
+    def get_counts(self, out=None, stream=None):
+        if out is not None and _is_torch_cuda(out):
+            _check(lib().rdx_get_counts(self._h, out.data_ptr(), 1, _stream_ptr(stream)), "rdx_get_counts")
+            return out
+        c = np.zeros((self.S, self.T), np.int32)
+        _check(lib().rdx_get_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_get_counts")
+        return c
+
+    def run(self, t_end: float, stream=None):
+        _check(lib().rdx_run(self._h, float(t_end), _stream_ptr(stream)), "rdx_run")
+
+    def step(self, n_windows: int, stream=None):
+        _check(lib().rdx_step(self._h, int(n_windows), _stream_ptr(stream)), "rdx_step")
+
+    def sync(self, stream=None):
+        _check(lib().rdx_sync(self._h, _stream_ptr(stream)), "rdx_sync")
+
+    def stats(self, stream=None) -> Stats:
+        st = _Stats()
+        _check(lib().rdx_get_stats(self._h, C.byref(st), _stream_ptr(stream)), "rdx_get_stats")
+        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index)
+
+    def geometry(self) -> dict:
+        T = self.T
+        out = dict(nbr=np.zeros((T, 4), np.int32), g=np.zeros((T, 4)), G=np.zeros(T),
+                   csplit=np.zeros((T, 4)), nav=np.zeros(T))
+        _check(lib().rdx_get_geometry(self._h, *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "csplit", "nav")]),
+               "rdx_get_geometry")
+        return out
+
+    def save(self, stream=None) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().rdx_save(self._h, None, C.byref(n), _stream_ptr(stream)), "rdx_save")
+        buf = C.create_string_buffer(n.value)
+        _check(lib().rdx_save(self._h, buf, C.byref(n), _stream_ptr(stream)), "rdx_save")
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes, stream=None):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().rdx_load(self._h, buf, len(blob), _stream_ptr(stream)), "rdx_load")
+
+
+# -- device self-tests of the random layer ------------------------------------
+def selftest_philox(ctr_key: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(ctr_key, np.uint32).reshape(-1, 6)
+    out = np.zeros((a.shape[0], 4), np.uint32)
+    _check(lib().rdx_selftest_philox(_np_ptr(a), _np_ptr(out), a.shape[0]), "rdx_selftest_philox")
+    return out
+
+
+def selftest_ln(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros_like(x)
+    _check(lib().rdx_selftest_ln(_np_ptr(x), _np_ptr(y), x.size), "rdx_selftest_ln")
+    return y
+
+
+def selftest_binom(seed: int, m: int, p: float, n: int, stream_id: int = 1, window: int = 0) -> np.ndarray:
+    out = np.zeros(n, np.int64)
+    _check(lib().rdx_selftest_binom(seed, stream_id, window, m, p, n, _np_ptr(out)), "rdx_selftest_binom")
+    return out

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on the same seeded inputs.  Integer counts and tallies must match bit
+for bit after every window (the oracle and the kernels compute the same
+sequence of IEEE-754 binary64 operations with fp contraction off)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1610_02258_amd import inputs as I
+from tests.meshes import mirror_pair, model, single_tet
+from tests.randmodels import random_counts, random_model
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rdx():
+    from paper_1610_02258_amd import rdx as R
+    R.lib()
+    return R
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(rdx, O, mesh, model_, seed, counts, tau=0.0):
+    sim = rdx.Sim(mesh, model_, seed, tau_override=tau)
+    ref = O.Instance(mesh, model_, seed, tau_override=tau)
+    assert sim.tau == ref.tau
+    sim.set_counts(counts)
+    ref.reset(counts)
+    return sim, ref
+
+
+def _assert_same(sim, ref, what=""):
+    got = sim.get_counts()
+    if not np.array_equal(got, ref.counts):
+        bad = np.argwhere(got != ref.counts)
+        s, t = bad[0]
+        raise AssertionError(f"{what}: {len(bad)} mismatches, first species {s} tet {t}: "
+                             f"gpu {got[s, t]} oracle {ref.counts[s, t]}")
+    st = sim.stats()
+    assert st.ssa_events == ref.tallies.ssa_events, (what, st.ssa_events, ref.tallies.ssa_events)
+    assert st.moves == ref.tallies.moves, (what, st.moves, ref.tallies.moves)
+    assert st.voxel_steps == ref.tallies.voxel_steps
+    assert st.window_index == ref.window and st.t == ref.t
+
+
+# ------------------------------------------------------- random layer ----
+
+def test_device_philox_matches(rdx, oracle_lib):
+    rows = [[0] * 6, [0xffffffff] * 6,
+            [0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344, 0xa4093822, 0x299f31d0]]
+    rng = np.random.default_rng(1)
+    rnd = rng.integers(0, 2**32, size=(5000, 6), dtype=np.uint64).astype(np.uint32)
+    inp = np.concatenate([np.array(rows, np.uint32), rnd])
+    out = rdx.selftest_philox(inp)
+    for j in range(inp.shape[0]):
+        np.testing.assert_array_equal(out[j], oracle_lib.philox4x32_10(inp[j, :4], inp[j, 4:]))
+
+
+def test_device_ln_bitwise(rdx, oracle_lib):
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.uniform(2.0**-53, 1.0, 100000),
+                        np.exp(rng.uniform(math.log(2.0**-53), 0.0, 100000)),
+                        [1.0, 0.5, 2.0**-53, 0.7071067811865476, 0.7071067811865475]])
+    y = rdx.selftest_ln(x)
+    ref = np.array([oracle_lib.ln(v) for v in x])
+    assert np.array_equal(y.view(np.int64), ref.view(np.int64))
+
+
+@pytest.mark.parametrize("m,p", [(7, 0.3), (40, 0.8), (1500, 0.2), (3, 1.0), (0, 0.4),
+                                 (1000, 1.0 - 2.0**-53), (25, 0.5)])
+def test_device_binomial_bitwise(rdx, oracle_lib, m, p):
+    got = rdx.selftest_binom(42, m, p, 20000, stream_id=3, window=9)
+    ref = oracle_lib.sample_binom(42, m, p, 20000, stream_id=3, window=9)
+    np.testing.assert_array_equal(got, ref)
+
+
+# -------------------------------------------------------- window parity ----
+
+def test_small_workload_parity(rdx, oracle_lib):
+    w = I.config_small()
+    _say("case: 6x6x6 box, A+B<->C, 10 ms (one truncated window), then 40 windows")
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    sim.run(w.t_end)
+    ref.run(w.t_end)
+    _assert_same(sim, ref, "run(10 ms)")
+    for k in range(40):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
+
+
+def test_small_workload_fast_reactions(rdx, oracle_lib):
+    """Same mesh with reactions 1000x faster: many SSA events per window."""
+    w = I.config_small()
+    m = I.model_abc(kf=1e9, kb=1e3).as_dict()
+    counts = I.place_uniform(w.mesh, [20000, 15000, 3000], 11)
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), m, 123, counts)
+    for k in range(6):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
+    assert ref.tallies.ssa_events > 100000
+
+
+@pytest.mark.parametrize("case", range(14))
+def test_random_models_parity(rdx, oracle_lib, case):
+    rng = np.random.default_rng(1000 + case)
+    S = int(rng.integers(1, 17))
+    R = int(rng.integers(0, 33))
+    n_regions = int(rng.integers(1, 4))
+    if case == 0:
+        S, R = 16, 32          # the largest tables
+    if case == 1:
+        S, R = 1, 0            # pure diffusion of one species
+    nx, ny, nz = (int(v) for v in rng.integers(1, 8, 3))
+    mesh = I.box_mesh(nx, ny, nz, 0.5e-6, jitter=0.1, seed=case)
+    mesh.region = rng.integers(0, n_regions, mesh.n_tets).astype(np.uint8)
+    md = random_model(rng, S, R, n_regions)
+    counts = random_counts(rng, S, mesh.n_tets, mean=float(rng.uniform(0.5, 30)))
+    _say(f"case {case}: T={mesh.n_tets} S={S} R={R} regions={n_regions}")
+    sim, ref = _pair(rdx, oracle_lib, mesh.as_dict(), md, 77 + case, counts)
+    t_end = 5.5 * ref.tau
+    sim.run(t_end)
+    ref.run(t_end)
+    _assert_same(sim, ref, "run 5.5 tau")
+    sim.step(3)
+    ref.step(3)
+    _assert_same(sim, ref, "3 more windows")
+
+
+def test_edge_cases(rdx, oracle_lib):
+    # all counts zero
+    w = I.config_small()
+    zero = np.zeros_like(w.counts)
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), 5, zero)
+    sim.step(3)
+    ref.step(3)
+    _assert_same(sim, ref, "zero counts")
+    assert sim.get_counts().sum() == 0
+    # a single tet: no neighbours, tau given
+    md = model([0, 0], [(["A"], ["B"], 5.0), (["B"], ["A"], 1.0)], ["A", "B"])
+    sim, ref = _pair(rdx, oracle_lib, single_tet(), md, 9, np.array([[50], [3]], np.int32), tau=0.01)
+    sim.step(20)
+    ref.step(20)
+    _assert_same(sim, ref, "single tet")
+    # mirror pair: p = 1 swaps every window
+    c0 = np.array([[37, 5]], np.int32)
+    sim, ref = _pair(rdx, oracle_lib, mirror_pair(), model([1e-12], [], ["A"]), 3, c0)
+    sim.step(3)
+    ref.step(3)
+    _assert_same(sim, ref, "mirror pair")
+    np.testing.assert_array_equal(sim.get_counts(), c0[:, ::-1])
+    # run to a time already reached is a no-op
+    sim.run(sim.stats().t)
+    assert sim.stats().windows == 3
+
+
+def test_checkpoint_resume_is_bit_identical(rdx, oracle_lib):
+    w = I.config_small()
+    m = I.model_abc(kf=1e8, kb=50.0).as_dict()
+    a = rdx.Sim(w.mesh.as_dict(), m, 31)
+    a.set_counts(w.counts)
+    a.step(12)
+    straight = a.get_counts()
+    b = rdx.Sim(w.mesh.as_dict(), m, 31)
+    b.set_counts(w.counts)
+    b.step(5)
+    blob = b.save()
+    c = rdx.Sim(w.mesh.as_dict(), m, 31)
+    c.load(blob)
+    c.step(7)
+    np.testing.assert_array_equal(c.get_counts(), straight)
+    assert c.stats().ssa_events == a.stats().ssa_events
+
+
+def test_device_pointer_io(rdx, oracle_lib):
+    torch = pytest.importorskip("torch")
+    w = I.config_small()
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), 2, w.counts)
+    dev = torch.from_numpy(w.counts.copy()).cuda()
+    stream = torch.cuda.current_stream()
+    sim.set_counts(dev, stream=stream)
+    sim.step(4, stream=stream)
+    out = torch.zeros_like(dev)
+    sim.get_counts(out, stream=stream)
+    torch.cuda.synchronize()
+    ref.step(4)
+    np.testing.assert_array_equal(out.cpu().numpy(), ref.counts)
+
+
+# ------------------------------------------------- full-size workloads ----
+
+def test_simple_model_full_size_prefix(rdx, oracle_lib):
+    """480,000-tet jittered box, 10 species / 12 reactions: the first windows
+    of the benchmarked run, compared on every count."""
+    w = I.config_simple()
+    _say(f"case: simple model, T={w.mesh.n_tets}")
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    for k in range(3):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
+
+
+def test_dendrite_full_size_prefix(rdx, oracle_lib):
+    w = I.config_dendrite()
+    _say(f"case: dendrite, T={w.mesh.n_tets}")
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    for k in range(2):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
