@@ -93,8 +93,6 @@ def main() -> int:
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    st0 = sim.stats(stream)
-    windows_per_step = st0.windows
 
     # timed region: K steps; HIP events on the launch stream bracket the window
     # launches of every step (the count reset before them is outside the pair)
@@ -113,11 +111,12 @@ def main() -> int:
     elapsed = time.perf_counter() - t_start
     # tallies of the last step (each step restarts from the same counts)
     st = sim.stats(stream)
+    windows_per_step = st.windows
     events_total = st.ssa_events * args.steps
     moves_total = st.moves * args.steps
     kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
     launches = windows_per_step * args.steps
-    avg_launch_s = kernel_ms * 1e-3 / launches
+    avg_launch_s = max(kernel_ms, 1e-6) * 1e-3 / launches
     voxel_steps = T * windows_per_step * args.steps
     bytes_per_launch = algorithmic_bytes(T, S, n_regions, st.moves / windows_per_step)
     achieved = bytes_per_launch / avg_launch_s / 1e9

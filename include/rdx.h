@@ -139,16 +139,17 @@ rdx_status rdx_get_sizes(const rdx_sim* sim, int32_t* n_tets, int32_t* n_species
                          int32_t* n_reactions);
 
 /* Derived set-up arrays, host pointers, each may be NULL: nbr [n_tets*4]
- * (-1 = boundary), g [n_tets*4], G [n_tets] (sum of g), csplit [n_tets*4]
- * (g_k / (g_k + ... + g_3), 0 on boundary faces), nav [n_tets] (N_A V[L]). */
+ * (-1 = boundary), g [n_tets*4], G [n_tets] (sum of g), cum [n_tets*4]
+ * (cumulative split fractions (g_0 + ... + g_k) / G for k < 3, cum_3 = 1),
+ * nav [n_tets] (N_A V[L]). */
 rdx_status rdx_get_geometry(const rdx_sim* sim, int32_t* nbr, double* g, double* G,
-                            double* csplit, double* nav);
+                            double* cum, double* nav);
 
 /* The same set-up arrays and tau computed on the host only, without creating
  * a simulation or touching a GPU (same layouts as rdx_get_geometry; *tau
  * receives the window).  Errors as rdx_create except RDX_ENOMEM/RDX_EHIP. */
 rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, double tau_override,
-                              int32_t* nbr, double* g, double* G, double* csplit, double* nav,
+                              int32_t* nbr, double* g, double* G, double* cum, double* nav,
                               double* tau);
 
 /* Checkpoint: counts, t, window index and tallies.  With buf == NULL, *len

@@ -180,9 +180,9 @@ class Instance:
         T = self.T
         out = dict(nbr=np.zeros((T, 4), np.int32), vol=np.zeros(T), area=np.zeros((T, 4)),
                    dist=np.zeros((T, 4)), g=np.zeros((T, 4)), G=np.zeros(T),
-                   csplit=np.zeros((T, 4)), nav=np.zeros(T))
+                   cum=np.zeros((T, 4)), nav=np.zeros(T))
         lib().os_get_geometry(self._h, *[_ptr(out[k]) for k in
-                                         ("nbr", "vol", "area", "dist", "g", "G", "csplit", "nav")])
+                                         ("nbr", "vol", "area", "dist", "g", "G", "cum", "nav")])
         return out
 
     def set_counts(self, counts: np.ndarray):

@@ -30,8 +30,14 @@
  *   - d_{S,tet,k} = D_S * A_k / (V_tet * h_k) (finite-volume coupling with
  *     A the shared face area and h the barycentre distance), boundary faces
  *     reflective;
- *   - the face split draws sequential conditional binomials in local face
- *     order; the last face with a nonzero coupling takes the remainder;
+ *   - the leavers and their faces are sampled per molecule for small counts:
+ *     with m <= 16, each of the m molecules draws one 32-bit uniform u and
+ *     goes to the first face k (before the last face present) with
+ *     u < p cum_k, else to the last face if u < p, else stays; with m > 16,
+ *     n = Bin(m, p) by inversion and each leaver draws one uniform for its
+ *     face (first k with u < cum_k, else the last face).  cum_k is the
+ *     left-to-right prefix sum of the face couplings over G.  Both are exact
+ *     samplers of binomial leavers split among neighbours by rate;
  *   - composition-rejection selection groups reactions by the binary
  *     exponent of their propensity (Slepoy, Thompson & Plimpton 2008);
  *   - random numbers are Philox4x32-10 (Salmon et al., SC'11), keyed by the
@@ -234,7 +240,7 @@ typedef struct {
   double* dist;      /* [T*4]  barycentre distances, m (0 on boundary faces) */
   double* g;         /* [T*4]  face coupling A_k/(V h_k), 1/m^2 (0 on boundary faces) */
   double* G;         /* [T]    sum of g over faces (right-to-left suffix sum) */
-  double* csplit;    /* [T*4]  conditional split probability g_k / (g_k + ... + g_3) */
+  double* cum;       /* [T*4]  cumulative split fraction (g_0 + ... + g_k) / G, k < 3; cum_3 = 1 */
   int32_t* last;     /* [T]    last face with g > 0, -1 if none */
   double* nav;       /* [T]    N_A * V[litre] */
   uint8_t* region;   /* [T] */
@@ -255,7 +261,7 @@ static void os_free_instance(os_instance* I)
 {
   if (!I) return;
   free(I->nbr); free(I->vol); free(I->area); free(I->dist); free(I->g);
-  free(I->G); free(I->csplit); free(I->last); free(I->nav); free(I->region);
+  free(I->G); free(I->cum); free(I->last); free(I->nav); free(I->region);
   free(I->D); free(I->lhs); free(I->rhs); free(I->kcst); free(I->order);
   free(I->deps);
   free(I);
@@ -317,7 +323,7 @@ int os_build(int32_t n_verts, const double* verts, int32_t T, const int32_t* tet
   I->dist = (double*)malloc(sizeof(double) * 4 * (size_t)T);
   I->g = (double*)malloc(sizeof(double) * 4 * (size_t)T);
   I->G = (double*)malloc(sizeof(double) * (size_t)T);
-  I->csplit = (double*)malloc(sizeof(double) * 4 * (size_t)T);
+  I->cum = (double*)malloc(sizeof(double) * 4 * (size_t)T);
   I->last = (int32_t*)malloc(sizeof(int32_t) * (size_t)T);
   I->nav = (double*)malloc(sizeof(double) * (size_t)T);
   I->region = (uint8_t*)malloc((size_t)T);
@@ -327,7 +333,7 @@ int os_build(int32_t n_verts, const double* verts, int32_t T, const int32_t* tet
   I->kcst = (double*)malloc(sizeof(double) * (size_t)(n_regions * R + 1));
   I->order = (int32_t*)malloc(sizeof(int32_t) * (size_t)(R + 1));
   I->deps = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(R + 1));
-  if (!I->nbr || !I->vol || !I->area || !I->dist || !I->g || !I->G || !I->csplit ||
+  if (!I->nbr || !I->vol || !I->area || !I->dist || !I->g || !I->G || !I->cum ||
       !I->last || !I->nav || !I->region || !I->D || !I->lhs || !I->rhs || !I->kcst ||
       !I->order || !I->deps) {
     os_free_instance(I);
@@ -426,7 +432,7 @@ int os_build(int32_t n_verts, const double* verts, int32_t T, const int32_t* tet
   }
   free(keys);
 
-  /* couplings g = A / (V h), suffix sums, conditional split probabilities */
+  /* couplings g = A / (V h), their total G (right-to-left), cumulative split fractions */
   for (int32_t i = 0; i < T; ++i) {
     double bi[3];
     os_barycentre(verts, tets + 4 * (size_t)i, bi);
@@ -448,16 +454,17 @@ int os_build(int32_t n_verts, const double* verts, int32_t T, const int32_t* tet
       I->dist[4 * (size_t)i + k] = h;
       g[k] = I->area[4 * (size_t)i + k] / (I->vol[i] * h);
     }
-    double suf[4];
-    suf[3] = g[3];
-    suf[2] = g[2] + suf[3];
-    suf[1] = g[1] + suf[2];
-    suf[0] = g[0] + suf[1];
-    I->G[i] = suf[0];
+    double G = g[3];
+    G = g[2] + G;
+    G = g[1] + G;
+    G = g[0] + G;
+    I->G[i] = G;
+    double pre = 0.0;
     I->last[i] = -1;
     for (int k = 0; k < 4; ++k) {
       I->g[4 * (size_t)i + k] = g[k];
-      I->csplit[4 * (size_t)i + k] = g[k] > 0.0 ? g[k] / suf[k] : 0.0;
+      pre = pre + g[k];
+      I->cum[4 * (size_t)i + k] = k == 3 ? 1.0 : (G > 0.0 ? pre / G : 0.0);
       if (g[k] > 0.0) I->last[i] = k;
     }
   }
@@ -483,7 +490,7 @@ double os_get_tau(const os_instance* I) { return I->tau; }
 
 /* Export the derived geometry for tests (arrays sized as in os_instance). */
 void os_get_geometry(const os_instance* I, int32_t* nbr, double* vol, double* area,
-                     double* dist, double* g, double* G, double* csplit, double* nav)
+                     double* dist, double* g, double* G, double* cum, double* nav)
 {
   size_t T = (size_t)I->T;
   if (nbr) memcpy(nbr, I->nbr, sizeof(int32_t) * 4 * T);
@@ -492,7 +499,7 @@ void os_get_geometry(const os_instance* I, int32_t* nbr, double* vol, double* ar
   if (dist) memcpy(dist, I->dist, sizeof(double) * 4 * T);
   if (g) memcpy(g, I->g, sizeof(double) * 4 * T);
   if (G) memcpy(G, I->G, sizeof(double) * T);
-  if (csplit) memcpy(csplit, I->csplit, sizeof(double) * 4 * T);
+  if (cum) memcpy(cum, I->cum, sizeof(double) * 4 * T);
   if (nav) memcpy(nav, I->nav, sizeof(double) * T);
 }
 
@@ -622,6 +629,48 @@ static int os_ssa_window(const os_instance* I, int32_t i, double tau_k, uint64_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Diffusion operator of one (tet, species): m trials of leaving with        */
+/* probability p, each leaver to a face in proportion to the face coupling,  */
+/* at most npost leavers.  Returns the number of leavers; out[k] receives    */
+/* the molecules sent across face k.                                         */
+/* ------------------------------------------------------------------------ */
+#define OS_SMALL_M 16
+
+static int os_pick_face(const os_instance* I, int32_t i, double u, double scale)
+{
+  int last = I->last[i];
+  for (int k = 0; k < last; ++k)
+    if (u < scale * I->cum[4 * (size_t)i + k]) return k;
+  return last;
+}
+
+static int64_t os_diffuse_leavers(const os_instance* I, int32_t i, int64_t m, double p,
+                                  int64_t npost, os_stream* st, int64_t out[4])
+{
+  int64_t n = 0;
+  if (m <= 0 || !(p > 0.0)) return 0;
+  if (m <= OS_SMALL_M) {
+    /* one uniform per molecule: leave to face k if it falls in that face's
+       share of [0, p); later leavers stay once npost have left */
+    for (int64_t j = 0; j < m; ++j) {
+      double u = os_u32_co(st);
+      if (u < p && n < npost) {
+        out[os_pick_face(I, i, u, p)] += 1;
+        n = n + 1;
+      }
+    }
+    return n;
+  }
+  n = os_binom(m, p, st);
+  if (n > npost) n = npost;
+  for (int64_t j = 0; j < n; ++j) {
+    double u = os_u32_co(st);
+    out[os_pick_face(I, i, u, 1.0)] += 1;
+  }
+  return n;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One window (Algorithm 1): reaction SSA then diffusion, all tets, with      */
 /* outflows taken from post-reaction counts and applied afterwards.          */
 /* counts: [S*T] species-major, in/out.  work: [S*T] scratch.               */
@@ -657,17 +706,7 @@ static int os_window(const os_instance* I, uint64_t seed, double tau_k, uint32_t
         }
         double p = (tau_k * I->D[s]) * G;
         if (p > 1.0) p = 1.0;
-        n = os_binom(m, p, &st);
-        if (n > N[s]) n = N[s];
-        int64_t rem = n;
-        int lastk = I->last[i];
-        for (int k = 0; k < 4 && rem > 0; ++k) {
-          if (!(I->g[4 * (size_t)i + k] > 0.0)) continue;
-          if (k == lastk) { out[k] = rem; rem = 0; break; }
-          int64_t nk = os_binom(rem, I->csplit[4 * (size_t)i + k], &st);
-          out[k] = nk;
-          rem -= nk;
-        }
+        n = os_diffuse_leavers(I, i, m, p, N[s], &st, out);
       }
       next[(size_t)s * T + i] += (int32_t)(N[s] - n);
       for (int k = 0; k < 4; ++k)

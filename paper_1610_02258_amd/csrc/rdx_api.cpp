@@ -3,6 +3,7 @@
 // host loop over window launches, checkpoints and error reporting.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -38,12 +39,16 @@ struct rdx_sim {
   int32_t* cnt[2] = {nullptr, nullptr};
   int cur = 0;
   int32_t* nbr = nullptr;
-  double* geo = nullptr;        // (G, c0, c1, c2) per tet
+  double* geo = nullptr;        // (G, cum0, cum1, cum2) per tet
   double* nav = nullptr;
   uint8_t* region = nullptr;
   DevModel* model = nullptr;
   unsigned long long* tally = nullptr;   // [2] events, moves
   int* err = nullptr;
+  int32_t* wl_tet = nullptr;    // [T] tets with an SSA event in the current window
+  int32_t* wl_cnt = nullptr;    // [S][T] their counts at the window start
+  int32_t* wl_count = nullptr;  // [2] list lengths, alternating by window parity
+  KModel km;
   double t = 0.0;
   int64_t window = 0;
   int64_t windows_run = 0;
@@ -75,6 +80,9 @@ void free_device(rdx_sim* s) {
   (void)hipFree(s->model);
   (void)hipFree(s->tally);
   (void)hipFree(s->err);
+  (void)hipFree(s->wl_tet);
+  (void)hipFree(s->wl_cnt);
+  (void)hipFree(s->wl_count);
 }
 
 DevModel make_dev_model(const HostInstance& I) {
@@ -95,9 +103,9 @@ DevModel make_dev_model(const HostInstance& I) {
       }
       m.delta[r][s] = (int8_t)(I.rhs[(size_t)r * S + s] - nu);
     }
-    m.order[r] = (int8_t)order;
-    m.r0[r] = (int8_t)r0;
-    m.r1[r] = (int8_t)(order == 2 ? r1 : -1);
+    const int b0 = r0 < 0 ? 0xff : r0;
+    const int b1 = (order == 2 && r1 >= 0) ? r1 : 0xff;
+    m.info[r] = order | (b0 << 8) | (b1 << 16);
     for (int reg = 0; reg < I.n_regions; ++reg) m.kcst[reg][r] = I.kcst[(size_t)reg * R + r];
   }
   // deps(R): reactions whose propensity reads a species that r changes
@@ -139,6 +147,12 @@ rdx_status launch_one(rdx_sim* s, double tau_k, hipStream_t stream) {
   a.window = (uint32_t)s->window;
   a.tau_k = tau_k;
   for (int sp = 0; sp < I.S; ++sp) a.tauD[sp] = tau_k * I.D[sp];
+  a.wl_tet = s->wl_tet;
+  a.wl_cnt = s->wl_cnt;
+  a.wl_count = s->wl_count + (s->window & 1);
+  a.wl_reset = s->wl_count + ((s->window + 1) & 1);
+  a.event_blocks = std::max(1, std::min((I.T + 63) / 64, 1024));
+  a.km = s->km;
   hipError_t e = launch_window(a, stream);
   if (e != hipSuccess) return set_error(RDX_EHIP, std::string("window launch: ") + hipGetErrorString(e));
   s->cur = 1 - s->cur;
@@ -176,16 +190,22 @@ rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t see
   std::vector<double> geo(4 * T);
   for (size_t i = 0; i < T; ++i) {
     geo[4 * i + 0] = I.G[i];
-    geo[4 * i + 1] = I.csplit[4 * i + 0];
-    geo[4 * i + 2] = I.csplit[4 * i + 1];
-    geo[4 * i + 3] = I.csplit[4 * i + 2];
+    geo[4 * i + 1] = I.cum[4 * i + 0];
+    geo[4 * i + 2] = I.cum[4 * i + 1];
+    geo[4 * i + 3] = I.cum[4 * i + 2];
   }
   DevModel dm = make_dev_model(I);
+  std::memset(&s->km, 0, sizeof s->km);
+  for (int r = 0; r < I.R; ++r) {
+    s->km.info[r] = dm.info[r];
+    s->km.kcst0[r] = dm.kcst[0][r];
+  }
   bool ok = dev_alloc(&s->cnt[0], S * T) == hipSuccess && dev_alloc(&s->cnt[1], S * T) == hipSuccess &&
             dev_alloc(&s->nbr, 4 * T) == hipSuccess && dev_alloc(&s->geo, 4 * T) == hipSuccess &&
             dev_alloc(&s->nav, T) == hipSuccess && dev_alloc(&s->region, T) == hipSuccess &&
             dev_alloc(&s->model, 1) == hipSuccess && dev_alloc(&s->tally, 2) == hipSuccess &&
-            dev_alloc(&s->err, 1) == hipSuccess;
+            dev_alloc(&s->err, 1) == hipSuccess && dev_alloc(&s->wl_tet, T) == hipSuccess &&
+            dev_alloc(&s->wl_cnt, S * T) == hipSuccess && dev_alloc(&s->wl_count, 2) == hipSuccess;
   if (!ok) {
     free_device(s);
     delete s;
@@ -202,6 +222,7 @@ rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t see
   if (e == hipSuccess) e = hipMemset(s->cnt[1], 0, sizeof(int32_t) * S * T);
   if (e == hipSuccess) e = hipMemset(s->tally, 0, sizeof(unsigned long long) * 2);
   if (e == hipSuccess) e = hipMemset(s->err, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(s->wl_count, 0, 2 * sizeof(int32_t));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_device(s);
@@ -238,6 +259,7 @@ rdx_status rdx_set_counts(rdx_sim* s, const int32_t* counts, int is_device_ptr, 
   RDX_HIP(hipMemsetAsync(s->cnt[1], 0, sizeof(int32_t) * n, st));
   RDX_HIP(hipMemsetAsync(s->tally, 0, sizeof(unsigned long long) * 2, st));
   RDX_HIP(hipMemsetAsync(s->err, 0, sizeof(int), st));
+  RDX_HIP(hipMemsetAsync(s->wl_count, 0, 2 * sizeof(int32_t), st));
   if (!is_device_ptr) RDX_HIP(hipStreamSynchronize(st));
   s->cur = 0;
   s->t = 0.0;
@@ -338,7 +360,7 @@ rdx_status rdx_get_sizes(const rdx_sim* s, int32_t* n_tets, int32_t* n_species, 
   return RDX_OK;
 }
 
-rdx_status rdx_get_geometry(const rdx_sim* s, int32_t* nbr, double* g, double* G, double* csplit,
+rdx_status rdx_get_geometry(const rdx_sim* s, int32_t* nbr, double* g, double* G, double* cum,
                             double* nav) {
   if (!s) return set_error(RDX_EINVAL, "null simulation handle");
   const HostInstance& I = s->host;
@@ -346,13 +368,13 @@ rdx_status rdx_get_geometry(const rdx_sim* s, int32_t* nbr, double* g, double* G
   if (nbr) std::memcpy(nbr, I.nbr.data(), sizeof(int32_t) * 4 * T);
   if (g) std::memcpy(g, I.g.data(), sizeof(double) * 4 * T);
   if (G) std::memcpy(G, I.G.data(), sizeof(double) * T);
-  if (csplit) std::memcpy(csplit, I.csplit.data(), sizeof(double) * 4 * T);
+  if (cum) std::memcpy(cum, I.cum.data(), sizeof(double) * 4 * T);
   if (nav) std::memcpy(nav, I.nav.data(), sizeof(double) * T);
   return RDX_OK;
 }
 
 rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, double tau_override,
-                              int32_t* nbr, double* g, double* G, double* csplit, double* nav,
+                              int32_t* nbr, double* g, double* G, double* cum, double* nav,
                               double* tau) {
   clear_error();
   HostInstance I;
@@ -363,7 +385,7 @@ rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, doub
   if (nbr) std::memcpy(nbr, I.nbr.data(), sizeof(int32_t) * 4 * T);
   if (g) std::memcpy(g, I.g.data(), sizeof(double) * 4 * T);
   if (G) std::memcpy(G, I.G.data(), sizeof(double) * T);
-  if (csplit) std::memcpy(csplit, I.csplit.data(), sizeof(double) * 4 * T);
+  if (cum) std::memcpy(cum, I.cum.data(), sizeof(double) * 4 * T);
   if (nav) std::memcpy(nav, I.nav.data(), sizeof(double) * T);
   if (tau) *tau = I.tau;
   return RDX_OK;

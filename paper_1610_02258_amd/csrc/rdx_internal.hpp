@@ -27,7 +27,7 @@ struct HostInstance {
   std::vector<int32_t> nbr;      // [T*4] neighbour across face k (opposite local vertex k), -1 boundary
   std::vector<double> g;         // [T*4] A_k / (V h_k), 0 on boundary faces
   std::vector<double> G;         // [T]   g_0 + (g_1 + (g_2 + g_3))
-  std::vector<double> csplit;    // [T*4] g_k / (g_k + ... + g_3), 0 on boundary faces
+  std::vector<double> cum;       // [T*4] (g_0 + ... + g_k) / G for k < 3, cum_3 = 1
   std::vector<double> nav;       // [T]   N_A * V[L]
   std::vector<uint8_t> region;   // [T]
   std::vector<double> D;         // [S]

@@ -1,7 +1,7 @@
 // rdx_kernels.hip -- gfx950 kernels of the operator-splitting reaction-diffusion
 // window ("Parallel STEPS", Algorithm 1), one lane per tetrahedron.
 //
-// Per window and tet the kernel does, in the paper's order:
+// Per window and tet, in the paper's order:
 //   1. load the tet's counts (species-major SoA, coalesced over tets);
 //   2. the reaction SSA operator: propensities of the tet's reactions, exact
 //      SSA events until the next one would fall outside the window, reaction
@@ -9,13 +9,13 @@
 //      FP64 time, occupancy O_S += N_S (dt - t_S) for every species an event
 //      changes, finalised at the window end;
 //   3. the diffusion operator for each diffusive species: mean occupancy
-//      Nbar = O_S / tau, leavers n = Bin(round(Nbar), tau D_S G) (stochastic
-//      rounding, clamped to the post-reaction count), split over the faces by
-//      sequential conditional binomials with probabilities g_k / sum_{j>=k} g_j;
-//   4. integer atomic adds of the remainder into the tet's own slot and of the
-//      face moves into the neighbours' slots of the next count buffer -- the
-//      single-GPU form of the paper's local application plus remote change
-//      buffers; integer addition makes the result independent of order.
+//      Nbar = O_S / tau, leavers Bin(round(Nbar), tau D_S G) (stochastic
+//      rounding, at most the post-reaction count), each leaver sent to a face
+//      with probability g_k / G (per-molecule draws for small counts);
+//   4. integer adds of the remainder and of the face moves into the next
+//      count buffer -- the single-GPU form of the paper's local application
+//      plus remote change buffers; integer addition makes the result
+//      independent of order.
 // Random numbers are Philox4x32-10 (Salmon et al., SC'11) with the counter
 // (draw call, stream, tet, window); stream 0 is the tet's SSA, stream 1+s the
 // diffusion of species s.  The logarithm and the binomial use only correctly
@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "rdx_internal.hpp"
 #include "rdx_kernels.hpp"
@@ -41,16 +42,15 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, x0);
-    const uint32_t lo0 = 0xD2511F53u * x0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
-    const uint32_t lo1 = 0xCD9E8D57u * x2;
-    const uint32_t y0 = hi1 ^ x1 ^ k0;
-    const uint32_t y2 = hi0 ^ x3 ^ k1;
+    // one 32x32->64 multiply each (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
     x0 = y0;
-    x1 = lo1;
+    x1 = (uint32_t)p1;
     x2 = y2;
-    x3 = lo0;
+    x3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }
@@ -87,6 +87,17 @@ struct Draw32 {
   __device__ Draw32(uint32_t key0, uint32_t key1, uint32_t stream, uint32_t t, uint32_t w)
       : k0(key0), k1(key1), sid(stream), tet(t), win(w), call(0), w0(0), w1(0), w2(0), w3(0),
         pos(4) {}
+  // Computes the stream's first Philox call up front, so that every item of a
+  // wave refills at the same program point (draw values are unchanged).
+  __device__ __forceinline__ void prime() {
+    w0 = call;
+    w1 = sid;
+    w2 = tet;
+    w3 = win;
+    philox4x32_10(w0, w1, w2, w3, k0, k1);
+    ++call;
+    pos = 0;
+  }
   __device__ __forceinline__ double u() {
     if (pos == 4) {
       w0 = call;
@@ -168,11 +179,14 @@ __device__ long long binom_core(long long m, double p, Draw32& st) {
   return total;
 }
 
+// One code path for both sides of 1/2 (the complement is taken by flipping),
+// so that lanes of a wave with different p do not run two copies.
 __device__ __forceinline__ long long binom(long long m, double p, Draw32& st) {
   if (m <= 0 || !(p > 0.0)) return 0;
   if (p >= 1.0) return m;
-  if (p > 0.5) return m - binom_core(m, 1.0 - p, st);
-  return binom_core(m, p, st);
+  const bool flip = p > 0.5;
+  const long long k = binom_core(m, flip ? 1.0 - p : p, st);
+  return flip ? m - k : k;
 }
 
 // ---------------------------------------------------------- propensity ----
@@ -190,30 +204,36 @@ __device__ __forceinline__ int select_count(const int (&N)[SMAX], int s) {
 
 // a_r = c_r h_r(N): c = k N_A V[L] (order 0), k (order 1), k / (N_A V[L])
 // (order 2); h = 1, N_A, N_A N_B or N_A (N_A - 1) / 2.  Values below 2^-1000
-// are taken as zero.
-template <int SMAX>
-__device__ __forceinline__ double propensity(const DevModel* __restrict__ M, int r, double k,
-                                             const int (&N)[SMAX], double nav, double inv_nav) {
-  const int order = M->order[r];
+// are taken as zero.  `info` is the packed reaction entry (uniform).
+__device__ __forceinline__ double mass_action(int info, double k, int n0, int n1, double nav,
+                                              double inv_nav) {
+  const int order = info & 0xff;
   double c, h;
   if (order == 0) {
     c = k * nav;
     h = 1.0;
   } else if (order == 1) {
     c = k;
-    h = (double)select_count<SMAX>(N, M->r0[r]);
+    h = (double)n0;
   } else {
     c = k * inv_nav;
-    const int n0 = select_count<SMAX>(N, M->r0[r]);
-    if (M->r0[r] == M->r1[r]) {
+    if (((info >> 8) & 0xff) == ((info >> 16) & 0xff)) {
       h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
     } else {
-      const int n1 = select_count<SMAX>(N, M->r1[r]);
       h = (double)n0 * (double)n1;
     }
   }
   const double a = c * h;
   return a >= 0x1p-1000 ? a : 0.0;
+}
+
+template <int SMAX>
+__device__ __forceinline__ double propensity(const DevModel* __restrict__ M, int r, double k,
+                                             const int (&N)[SMAX], double nav, double inv_nav) {
+  const int info = M->info[r];
+  const int n0 = select_count<SMAX>(N, (info >> 8) & 0xff);
+  const int n1 = select_count<SMAX>(N, (info >> 16) & 0xff);
+  return mass_action(info, k, n0, n1, nav, inv_nav);
 }
 
 // Composition: groups of reactions with equal binary exponent, visited from
@@ -279,147 +299,450 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + slot;
 }
 
-// ------------------------------------------------------- window kernel ----
+// ------------------------------------------------------- window kernels ----
+// A window is two launches, one wave (64 lanes) per block, one lane per tet.
+//
+// window_fast_kernel, over all tets: every global load of the tet is issued up
+// front (counts, N_A V, neighbours, couplings); the propensities and their sum
+// a0 use the model tables held in the kernel arguments; the first SSA waiting
+// time is drawn.  A tet whose first event falls inside the window is appended
+// to a worklist with its counts; for every other tet no count changes, the
+// mean occupancy is the count itself, and its diffusion items are sampled
+// here.  window_event_kernel then runs the full SSA (composition-rejection,
+// occupancy) and the diffusion of the listed tets only.  The heavy per-tet SSA
+// state (propensities, occupancy clocks) thus lives only in the small second
+// kernel, and the all-tets kernel keeps a small register footprint.
+//
+// Diffusion items: every (tet, species) pair with something to sample becomes
+// an item; a wave-level prefix sum over the lanes' item counts packs them into
+// LDS, and the 64 lanes then walk the packed list, so a wave spends one pass
+// per 64 items instead of one pass per species.
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// Leavers of one item and their faces.  m = nbar stochastically rounded (a
+// draw only when nbar is fractional).  With m <= 16 every molecule draws one
+// 32-bit uniform u and leaves when u < p, to the first face k before the last
+// face present with u < p cum_k, else to the last face; once npost molecules
+// have left the rest stay.  With m > 16, n = min(Bin(m, p), npost) leavers
+// each draw one uniform for their face (same rule with p replaced by 1).
+// Both are exact samplers of binomial leavers split among the faces in
+// proportion to the face couplings.  ga = (G, cum0), gb = (cum1, cum2).
+constexpr int kSmallM = 16;
+
+struct ItemMoves {
+  int n, o0, o1, o2, o3;
+};
+
+__device__ __forceinline__ ItemMoves sample_item(const WindowArgs& A, int ti, int s, double nbar,
+                                                 int npost, int4 nb, double2 ga, double2 gb,
+                                                 double tauDs) {
+  const int last = nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
+  Draw32 sp(A.key0, A.key1, 1u + (uint32_t)s, (uint32_t)ti, A.window);
+  sp.prime();
+  const double fl = floor(nbar);
+  const double frac = nbar - fl;
+  long long m = (long long)fl;
+  if (frac > 0.0) {
+    if (sp.u() < frac) m += 1;
+  }
+  double p = tauDs * ga.x;
+  if (p > 1.0) p = 1.0;
+  long long trials;
+  double scale;
+  if (m <= kSmallM) {
+    trials = m;
+    scale = p;
+  } else {
+    long long nb_ = binom(m, p, sp);
+    trials = nb_ > npost ? (long long)npost : nb_;
+    scale = 1.0;
+  }
+  const double t0 = scale * ga.y, t1 = scale * gb.x, t2 = scale * gb.y;
+  int n = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+  for (long long j = 0; j < trials; ++j) {
+    const double u = sp.u();
+    if (u < scale && n < npost) {
+      const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
+      o0 += f == 0;
+      o1 += f == 1;
+      o2 += f == 2;
+      o3 += f == 3;
+      ++n;
+    }
+  }
+  return ItemMoves{n, o0, o1, o2, o3};
+}
+
+// Tile schedule of a persistent block: the blocks are dispatched round-robin
+// over the 8 XCDs, so XCD x (= block % 8) owns one contiguous range of tiles
+// (its L2 then sees neighbouring tets), shared round-robin by its blocks.
+struct TileRange {
+  int first, end, stride;
+};
+
+__device__ __forceinline__ TileRange tile_range(int b, int G, int n_tiles) {
+  if (G < 8 || n_tiles < 8) return TileRange{b, n_tiles, G};
+  const int x = b & 7, j = b >> 3;
+  const int Gx = (G - x + 7) >> 3;  // blocks with block % 8 == x
+  const int lo = (int)(((long long)n_tiles * x) >> 3);
+  const int hi = (int)(((long long)n_tiles * (x + 1)) >> 3);
+  return TileRange{lo + j, hi, Gx};
+}
+
+// Everything one lane reads from global memory for its tet.
+template <int SMAX>
+struct TetData {
+  int N[SMAX];
+  double nav;
+  int4 nb;
+  double2 ga, gb;  // (G, cum0), (cum1, cum2)
+  int reg;
+};
+
+template <int SMAX>
+__device__ __forceinline__ void load_tet(const WindowArgs& A, int i, TetData<SMAX>& d) {
+  const bool active = i < A.T;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s)
+    d.N[s] = (active && s < A.S) ? A.cnt_in[(size_t)s * A.T + i] : 0;
+  d.nav = 1.0;
+  d.nb = make_int4(-1, -1, -1, -1);
+  d.ga = make_double2(0.0, 0.0);
+  d.gb = make_double2(0.0, 0.0);
+  d.reg = 0;
+  if (active) {
+    d.nav = A.nav[i];
+    d.nb = reinterpret_cast<const int4*>(A.nbr)[i];
+    const double2* gp = reinterpret_cast<const double2*>(A.geo) + 2 * (size_t)i;
+    d.ga = gp[0];
+    d.gb = gp[1];
+    if (A.region) d.reg = A.region[i];
+  }
+}
+
+// Persistent: each block (one wave) walks its tiles of 64 tets, issuing the
+// loads of the next tile before working on the current one.
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kBlock) window_kernel(const WindowArgs A) {
+__global__ void __launch_bounds__(kWave) window_fast_kernel(const WindowArgs A) {
+  __shared__ int s_acc[SMAX][kWave];         // counts (propensities), then next counts of own tets
+  __shared__ double s_tauD[SMAX];
+  __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
+  __shared__ int s_m[SMAX * kWave];          // count of the item's species
+  __shared__ int4 s_nbr[kWave];
+  __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants when the model has regions
+
+  const int lane = threadIdx.x;
+  const int T = A.T, S = A.S, R = A.R;
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? A.tauD[s] : 0.0;
+  }
+  if (A.region) {
+    for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
+      s_kc[x / RMAX][x % RMAX] = A.model->kcst[x / RMAX][x % RMAX];
+  }
+  __syncthreads();
+
+  const int n_tiles = (T + kWave - 1) / kWave;
+  const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
+  TetData<SMAX> cur, nxt;
+  if (tr.first < tr.end) load_tet<SMAX>(A, tr.first * kWave + lane, cur);
+  unsigned long long n_moved = 0;
+  int errbits = 0;
+
+  for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
+    if (tile + tr.stride < tr.end) load_tet<SMAX>(A, (tile + tr.stride) * kWave + lane, nxt);
+    const int base = tile * kWave;
+    const int i = base + lane;
+    const bool active = i < T;
+
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      s_acc[s][lane] = cur.N[s];
+      if (cur.N[s] != 0) A.cnt_in[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
+      if (cur.N[s] > kCountCap) errbits |= kErrOverflow;
+    }
+
+    // propensities a_r = c_r h_r(N), summed in reaction order; the reaction
+    // table is uniform (kernel arguments, scalar loads).  Two copies of the
+    // loop on the uniform region flag keep each rate-constant load in one
+    // address space (LDS table with regions, kernel arguments without).
+    const double nav = cur.nav;
+    const double inv_nav = 1.0 / nav;
+    const int reg = cur.reg;
+    auto sum_propensities = [&](auto with_regions) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) {
+        if (r < R) {
+          const int info = A.km.info[r];
+          double k;
+          if constexpr (decltype(with_regions)::value) k = s_kc[reg][r];
+          else k = A.km.kcst0[r];
+          const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+          const int n0 = s0 < SMAX ? s_acc[s0][lane] : 0;
+          const int n1 = s1 < SMAX ? s_acc[s1][lane] : 0;
+          acc = acc + mass_action(info, k, n0, n1, nav, inv_nav);
+        }
+      }
+      return acc;
+    };
+    const double a0 = A.region ? sum_propensities(std::true_type{}) : sum_propensities(std::false_type{});
+
+    // first waiting time: does an event fall inside the window?
+    bool event = false;
+    if (active && a0 > 0.0) {
+      Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
+      const double u = st.oc();
+      const double t_reac = -ln_basic(u) / a0;
+      event = !(0.0 + t_reac > A.tau_k);
+    }
+    const unsigned long long ballot = __ballot(event);
+    if (ballot) {
+      int slot = 0;
+      if (lane == 0) slot = atomicAdd(A.wl_count, (int)__popcll(ballot));
+      slot = __shfl(slot, 0) + (int)__popcll(ballot & ((1ull << lane) - 1ull));
+      if (event) {
+        A.wl_tet[slot] = i;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s)
+          if (s < S) A.wl_cnt[(size_t)s * T + slot] = cur.N[s];
+      }
+    }
+
+    // no event: Nbar = N; items for the diffusion operator.  The accumulator
+    // starts with what cannot leave (the event kernel handles listed tets).
+    uint32_t mask = 0;
+    s_nbr[lane] = cur.nb;
+    s_geo[0][lane] = cur.ga;
+    s_geo[1][lane] = cur.gb;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      int start = 0;
+      if (active && !event && s < S) {
+        if (A.tauD[s] > 0.0 && cur.ga.x > 0.0 && cur.N[s] > 0) mask |= 1u << s;
+        else start = cur.N[s];
+      }
+      s_acc[s][lane] = start;
+    }
+    const int cnt = __popc(mask);
+    const int incl = wave_inclusive_scan(cnt);
+    const int total = __shfl(incl, kWave - 1);
+    int pos = incl - cnt;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+      if ((mask >> s) & 1u) {
+        s_item[pos] = (uint16_t)((lane << 4) | s);
+        s_m[pos] = cur.N[s];
+        ++pos;
+      }
+    __syncthreads();
+
+    for (int j = lane; j < total; j += kWave) {
+      const int it = s_item[j];
+      const int L = it >> 4, sp = it & 15;
+      const int m = s_m[j];
+      const int4 tnb = s_nbr[L];
+      const ItemMoves mv = sample_item(A, base + L, sp, (double)m, m, tnb, s_geo[0][L],
+                                       s_geo[1][L], s_tauD[sp]);
+      // own remainder and moves to the tile's own tets go to LDS, the rest
+      // to the next count buffer
+      int32_t* __restrict__ out_s = A.cnt_out + (size_t)sp * T;
+      if (m != mv.n) atomicAdd(&s_acc[sp][L], m - mv.n);
+#define RDX_DEPOSIT(t, v)                                               \
+      if (v) {                                                          \
+        const unsigned off = (unsigned)((t) - base);                     \
+        if (off < (unsigned)kWave) atomicAdd(&s_acc[sp][off], (v));      \
+        else atomicAdd(out_s + (t), (v));                                \
+      }
+      RDX_DEPOSIT(tnb.x, mv.o0)
+      RDX_DEPOSIT(tnb.y, mv.o1)
+      RDX_DEPOSIT(tnb.z, mv.o2)
+      RDX_DEPOSIT(tnb.w, mv.o3)
+#undef RDX_DEPOSIT
+      n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+    }
+    __syncthreads();
+    // coalesced flush of the tile's own tets (other tiles add into them too)
+    if (active) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        const int v = s < S ? s_acc[s][lane] : 0;
+        if (v != 0) atomicAdd(A.cnt_out + (size_t)s * T + i, v);
+      }
+    }
+    __syncthreads();  // LDS is rebuilt for the next tile
+    cur = nxt;
+  }
+
+  const unsigned long long mv_sum = wave_sum(n_moved);
+  if (lane == 0 && mv_sum) atomicAdd(A.tally + 1, mv_sum);
+  if (errbits) atomicOr(A.err, errbits);
+}
+
+template <int SMAX, int RMAX>
+__global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A) {
   __shared__ double s_kc[kMaxRegions][RMAX];
   __shared__ int8_t s_delta[RMAX][SMAX];
   __shared__ unsigned long long s_deps[RMAX];
+  __shared__ double s_tauD[SMAX];
+  __shared__ double s_nbar[SMAX][kWave];     // mean occupancy of item (lane, s)
+  __shared__ int s_npost[SMAX][kWave];       // post-reaction count of item (lane, s)
+  __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
+  __shared__ int4 s_nbr[kWave];
+  __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
+  __shared__ int s_tet[kWave];
+
+  const int lane = threadIdx.x;
+  const int n_work = *A.wl_count;
+  if (blockIdx.x == 0 && lane == 0) *A.wl_reset = 0;  // the next window's list starts empty
+  if ((int)blockIdx.x * kWave >= n_work) return;      // whole block idle
+
   const DevModel* __restrict__ M = A.model;
-  for (int x = threadIdx.x; x < kMaxRegions * RMAX; x += kBlock)
+  for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
     s_kc[x / RMAX][x % RMAX] = M->kcst[x / RMAX][x % RMAX];
-  for (int x = threadIdx.x; x < RMAX * SMAX; x += kBlock)
+  for (int x = lane; x < RMAX * SMAX; x += kWave)
     s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
-  for (int x = threadIdx.x; x < RMAX; x += kBlock) s_deps[x] = M->deps[x];
+  for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
+  if (lane < SMAX) s_tauD[lane] = A.tauD[lane];
   __syncthreads();
 
   const int T = A.T, S = A.S, R = A.R;
-  const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const double tau = A.tau_k;
   unsigned long long n_ev = 0, n_moved = 0;
   int errbits = 0;
 
-  if (i < T) {
-    int N[SMAX];
+  for (int e0 = blockIdx.x * kWave; e0 < n_work; e0 += gridDim.x * kWave) {
+    const int e = e0 + lane;
+    const bool active = e < n_work;
+    const int i = active ? A.wl_tet[e] : 0;
+    uint32_t mask = 0;
+    if (active) {
+      int N[SMAX];
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      N[s] = 0;
-      if (s < S) {
-        int32_t* p = A.cnt_in + (size_t)s * T + i;
-        const int v = *p;
-        N[s] = v;
-        if (v != 0) *p = 0;  // the buffer is the next window's (zeroed) target
-      }
-    }
-    const int reg = A.region ? (int)A.region[i] : 0;
-    const double nav = A.nav[i];
-    const double inv_nav = 1.0 / nav;
-    double a[RMAX];
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      a[r] = r < R ? propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav) : 0.0;
-
-    // ---- reaction SSA operator over [0, tau_k] ----
-    double O[SMAX], tS[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      O[s] = 0.0;
-      tS[s] = 0.0;
-    }
-    uint32_t touched = 0;
-    const double tau = A.tau_k;
-    Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
-    double dt = 0.0;
-    for (;;) {
-      double a0 = 0.0;
+      for (int s = 0; s < SMAX; ++s) N[s] = s < S ? A.wl_cnt[(size_t)s * T + e] : 0;
+      const int reg = A.region ? (int)A.region[i] : 0;
+      const double nav = A.nav[i];
+      const int4 nb = reinterpret_cast<const int4*>(A.nbr)[i];
+      const double2* gp = reinterpret_cast<const double2*>(A.geo) + 2 * (size_t)i;  // (G, cum0), (cum1, cum2)
+      const double2 ga = gp[0], gb = gp[1];
+      const double inv_nav = 1.0 / nav;
+      double a[RMAX];
 #pragma unroll
       for (int r = 0; r < RMAX; ++r)
-        if (r < R) a0 = a0 + a[r];
-      if (!(a0 > 0.0)) break;
-      const double u = st.oc();
-      const double t_reac = -ln_basic(u) / a0;
-      if (dt + t_reac > tau) break;
-      const int rn = cr_select<RMAX>(a, R, a0, st);
-      dt = dt + t_reac;
+        a[r] = r < R ? propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav) : 0.0;
+
+      // ---- reaction SSA operator over [0, tau_k] ----
+      double O[SMAX], tS[SMAX];
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) {
-        if (s < S) {
-          const int d = s_delta[rn][s];
-          if (d != 0) {
-            O[s] = O[s] + (double)N[s] * (dt - tS[s]);
-            tS[s] = dt;
-            touched |= 1u << s;
-            N[s] += d;
-            if (N[s] > kCountCap) errbits |= kErrOverflow;
+        O[s] = 0.0;
+        tS[s] = 0.0;
+      }
+      uint32_t touched = 0;
+      Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
+      double dt = 0.0;
+      for (;;) {
+        double a0 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+          if (r < R) a0 = a0 + a[r];
+        if (!(a0 > 0.0)) break;
+        const double u = st.oc();
+        const double t_reac = -ln_basic(u) / a0;
+        if (dt + t_reac > tau) break;
+        const int rn = cr_select<RMAX>(a, R, a0, st);
+        dt = dt + t_reac;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          if (s < S) {
+            const int d = s_delta[rn][s];
+            if (d != 0) {
+              O[s] = O[s] + (double)N[s] * (dt - tS[s]);
+              tS[s] = dt;
+              touched |= 1u << s;
+              N[s] += d;
+              if (N[s] > kCountCap) errbits |= kErrOverflow;
+            }
           }
         }
-      }
-      const unsigned long long dep = s_deps[rn];
+        const unsigned long long dep = s_deps[rn];
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
-      ++n_ev;
-      if (errbits) break;
-      if (n_ev >= (unsigned long long)kEventCap) {
-        errbits |= kErrEvents;
-        break;
+        for (int r = 0; r < RMAX; ++r)
+          if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
+        ++n_ev;
+        if (errbits) break;
+        if (n_ev >= (unsigned long long)kEventCap) {
+          errbits |= kErrEvents;
+          break;
+        }
+      }
+
+      // ---- mean occupancies; items for the diffusion operator ----
+      s_tet[lane] = i;
+      s_nbr[lane] = nb;
+      s_geo[0][lane] = ga;
+      s_geo[1][lane] = gb;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        if (s >= S) continue;
+        double nbar;
+        if ((touched >> s) & 1u) {
+          O[s] = O[s] + (double)N[s] * (tau - tS[s]);
+          nbar = O[s] / tau;
+        } else {
+          nbar = (double)N[s];
+        }
+        if (s_tauD[s] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
+          mask |= 1u << s;
+          s_nbar[s][lane] = nbar;
+          s_npost[s][lane] = N[s];
+        } else if (N[s] != 0) {
+          atomicAdd(A.cnt_out + (size_t)s * T + i, N[s]);  // nothing can leave
+        }
       }
     }
+    const int cnt = __popc(mask);
+    const int incl = wave_inclusive_scan(cnt);
+    const int total = __shfl(incl, kWave - 1);
+    int pos = incl - cnt;
 #pragma unroll
     for (int s = 0; s < SMAX; ++s)
-      if ((touched >> s) & 1u) O[s] = O[s] + (double)N[s] * (tau - tS[s]);
-
-    // ---- diffusion operator ----
-    const int4 nb = reinterpret_cast<const int4*>(A.nbr)[i];
-    const double2* gp = reinterpret_cast<const double2*>(A.geo) + 2 * (size_t)i;
-    const double2 ga = gp[0], gb = gp[1];
-    const double G = ga.x;  // sum of the face couplings
-    const int last = nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : (nb.x >= 0 ? 0 : -1)));
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      if (s >= S) continue;
-      long long n = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-      if (A.tauD[s] > 0.0 && G > 0.0) {
-        Draw32 sp(A.key0, A.key1, 1u + (uint32_t)s, (uint32_t)i, A.window);
-        const double Nbar = ((touched >> s) & 1u) ? O[s] / tau : (double)N[s];
-        const double fl = floor(Nbar);
-        const double frac = Nbar - fl;
-        long long m = (long long)fl;
-        if (frac > 0.0) {
-          if (sp.u() < frac) m += 1;
-        }
-        double p = A.tauD[s] * G;
-        if (p > 1.0) p = 1.0;
-        n = binom(m, p, sp);
-        if (n > N[s]) n = N[s];
-        long long rem = n;
-        if (rem > 0 && nb.x >= 0) {
-          if (last == 0) { o0 = rem; rem = 0; }
-          else { o0 = binom(rem, ga.y, sp); rem -= o0; }
-        }
-        if (rem > 0 && nb.y >= 0) {
-          if (last == 1) { o1 = rem; rem = 0; }
-          else { o1 = binom(rem, gb.x, sp); rem -= o1; }
-        }
-        if (rem > 0 && nb.z >= 0) {
-          if (last == 2) { o2 = rem; rem = 0; }
-          else { o2 = binom(rem, gb.y, sp); rem -= o2; }
-        }
-        if (rem > 0 && nb.w >= 0) { o3 = rem; rem = 0; }
-      }
-      int32_t* out = A.cnt_out + (size_t)s * T;
-      const int keep = N[s] - (int)n;
-      if (keep != 0) atomicAdd(out + i, keep);
-      if (o0) atomicAdd(out + nb.x, (int)o0);
-      if (o1) atomicAdd(out + nb.y, (int)o1);
-      if (o2) atomicAdd(out + nb.z, (int)o2);
-      if (o3) atomicAdd(out + nb.w, (int)o3);
-      n_moved += (unsigned long long)(o0 + o1 + o2 + o3);
+      if ((mask >> s) & 1u) s_item[pos++] = (uint16_t)((lane << 4) | s);
+    __syncthreads();
+    for (int j = lane; j < total; j += kWave) {
+      const int it = s_item[j];
+      const int L = it >> 4, s = it & 15;
+      const int ti = s_tet[L];
+      const int npost = s_npost[s][L];
+      const int4 tnb = s_nbr[L];
+      const ItemMoves mv = sample_item(A, ti, s, s_nbar[s][L], npost, tnb, s_geo[0][L],
+                                       s_geo[1][L], s_tauD[s]);
+      int32_t* out_s = A.cnt_out + (size_t)s * T;
+      if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
+      if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
+      if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
+      if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
+      if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
+      n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
     }
+    __syncthreads();  // the LDS item list is rebuilt for the next 64 entries
   }
 
   const unsigned long long ev_sum = wave_sum(n_ev);
   const unsigned long long mv_sum = wave_sum(n_moved);
-  if ((threadIdx.x & 63) == 0) {
+  if (lane == 0) {
     if (ev_sum) atomicAdd(A.tally + 0, ev_sum);
     if (mv_sum) atomicAdd(A.tally + 1, mv_sum);
   }
@@ -456,19 +779,40 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
-hipError_t launch_window(const WindowArgs& a, hipStream_t stream) {
-  const dim3 grid(grid_for(a.T)), block(kBlock);
-  if (a.S <= 4 && a.R <= 4)
-    hipLaunchKernelGGL((window_kernel<4, 4>), grid, block, 0, stream, a);
-  else if (a.S <= 8 && a.R <= 8)
-    hipLaunchKernelGGL((window_kernel<8, 8>), grid, block, 0, stream, a);
-  else if (a.S <= 12 && a.R <= 12)
-    hipLaunchKernelGGL((window_kernel<12, 12>), grid, block, 0, stream, a);
-  else if (a.S <= 16 && a.R <= 24)
-    hipLaunchKernelGGL((window_kernel<16, 24>), grid, block, 0, stream, a);
-  else
-    hipLaunchKernelGGL((window_kernel<16, 32>), grid, block, 0, stream, a);
+// Persistent grid of the all-tets kernel: as many one-wave blocks as the
+// device holds at once (occupancy x compute units), rounded down to a
+// multiple of the 8 XCDs, never more than there are tiles.
+template <int SMAX, int RMAX>
+int fast_grid(int n_tiles) {
+  static const int resident = [] {
+    int dev = 0, n_cu = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&window_fast_kernel<SMAX, RMAX>), kWave, 0);
+    return n_cu > 0 && per_cu > 0 ? n_cu * per_cu : 2048;
+  }();
+  int g = resident < n_tiles ? resident : n_tiles;
+  if (g >= 8) g &= ~7;
+  return g > 0 ? g : 1;
+}
+
+template <int SMAX, int RMAX>
+hipError_t launch_pair(const WindowArgs& a, hipStream_t stream) {
+  const int n_tiles = (a.T + kWave - 1) / kWave;
+  hipLaunchKernelGGL((window_fast_kernel<SMAX, RMAX>), dim3((unsigned)fast_grid<SMAX, RMAX>(n_tiles)),
+                     dim3(kWave), 0, stream, a);
+  hipLaunchKernelGGL((window_event_kernel<SMAX, RMAX>), dim3((unsigned)a.event_blocks), dim3(kWave), 0,
+                     stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_window(const WindowArgs& a, hipStream_t stream) {
+  if (a.S <= 4 && a.R <= 4) return launch_pair<4, 4>(a, stream);
+  if (a.S <= 8 && a.R <= 8) return launch_pair<8, 8>(a, stream);
+  if (a.S <= 12 && a.R <= 12) return launch_pair<12, 12>(a, stream);
+  if (a.S <= 16 && a.R <= 24) return launch_pair<16, 24>(a, stream);
+  return launch_pair<16, 32>(a, stream);
 }
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {

@@ -2,7 +2,7 @@
 // face adjacency of the tetrahedral mesh, tet volumes, face couplings
 // g_k = A_k / (V h_k) (finite-volume coupling: shared-face area over tet
 // volume times barycentre distance), the per-tet total G = sum_k g_k, the
-// conditional face-split probabilities, N_A V[L] per tet, and the window
+// cumulative face-split fractions, N_A V[L] per tet, and the window
 // tau = min over (S, tet) of 1/d_{S,tet} with d_{S,tet} = D_S G_tet.
 //
 // Every floating-point expression is written as a fixed sequence of single
@@ -202,9 +202,9 @@ rdx_status build_instance(const rdx_mesh* mesh, const rdx_model* model, double t
     a = b;
   }
 
-  // couplings, totals (right-to-left suffix sums), conditional split probabilities
+  // couplings, their total, cumulative split fractions
   I.g.assign(4 * (size_t)T, 0.0);
-  I.csplit.assign(4 * (size_t)T, 0.0);
+  I.cum.assign(4 * (size_t)T, 0.0);
   I.G.assign((size_t)T, 0.0);
   for (int32_t i = 0; i < T; ++i) {
     Vec3 bi = barycentre(verts, tets + 4 * (size_t)i);
@@ -221,15 +221,17 @@ rdx_status build_instance(const rdx_mesh* mesh, const rdx_model* model, double t
       }
       g[k] = area[4 * (size_t)i + k] / (vol[i] * h);
     }
-    double suffix[4];
-    suffix[3] = g[3];
-    suffix[2] = g[2] + suffix[3];
-    suffix[1] = g[1] + suffix[2];
-    suffix[0] = g[0] + suffix[1];
-    I.G[i] = suffix[0];
+    // G = g0 + (g1 + (g2 + g3)); cum_k = (g0 + ... + gk) / G summed left to right
+    double G = g[3];
+    G = g[2] + G;
+    G = g[1] + G;
+    G = g[0] + G;
+    I.G[i] = G;
+    double prefix = 0.0;
     for (int k = 0; k < 4; ++k) {
       I.g[4 * (size_t)i + k] = g[k];
-      I.csplit[4 * (size_t)i + k] = g[k] > 0.0 ? g[k] / suffix[k] : 0.0;
+      prefix = prefix + g[k];
+      I.cum[4 * (size_t)i + k] = k == 3 ? 1.0 : (G > 0.0 ? prefix / G : 0.0);
     }
   }
 

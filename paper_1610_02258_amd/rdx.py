@@ -153,10 +153,10 @@ def setup_geometry(mesh: dict, model: dict, tau_override: float = 0.0) -> dict:
     """Host-only set-up arrays (adjacency, couplings, tau); no GPU needed."""
     m, md, keep, T, S, R = _marshal(mesh, model)
     out = dict(nbr=np.zeros((T, 4), np.int32), g=np.zeros((T, 4)), G=np.zeros(T),
-               csplit=np.zeros((T, 4)), nav=np.zeros(T))
+               cum=np.zeros((T, 4)), nav=np.zeros(T))
     tau = C.c_double()
     _check(lib().rdx_setup_geometry(C.byref(m), C.byref(md), float(tau_override),
-                                    *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "csplit", "nav")],
+                                    *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "cum", "nav")],
                                     C.byref(tau)), "rdx_setup_geometry")
     out["tau"] = tau.value
     return out
@@ -229,8 +229,8 @@ class Sim:
     def geometry(self) -> dict:
         T = self.T
         out = dict(nbr=np.zeros((T, 4), np.int32), g=np.zeros((T, 4)), G=np.zeros(T),
-                   csplit=np.zeros((T, 4)), nav=np.zeros(T))
-        _check(lib().rdx_get_geometry(self._h, *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "csplit", "nav")]),
+                   cum=np.zeros((T, 4)), nav=np.zeros(T))
+        _check(lib().rdx_get_geometry(self._h, *[_np_ptr(out[k]) for k in ("nbr", "g", "G", "cum", "nav")]),
                "rdx_get_geometry")
         return out
 

@@ -83,6 +83,6 @@ def test_setup_matches_oracle_bitwise(rdx, oracle_lib, make):
     ours = rdx.setup_geometry(mesh.as_dict(), model)
     inst = oracle_lib.Instance(mesh.as_dict(), model, 0)
     ref = inst.geometry()
-    for k in ("nbr", "g", "G", "csplit", "nav"):
+    for k in ("nbr", "g", "G", "cum", "nav"):
         np.testing.assert_array_equal(ours[k], ref[k], err_msg=k)
     assert ours["tau"] == inst.tau

@@ -73,13 +73,15 @@ def test_invariants(oracle_lib, jitter):
             assert geo["area"][i, k] == pytest.approx(geo["area"][j, kb], rel=1e-12)
             assert geo["dist"][i, k] == geo["dist"][j, kb]
             assert geo["vol"][i] * geo["g"][i, k] == pytest.approx(geo["vol"][j] * geo["g"][j, kb], rel=1e-12)
-    # G is the sum of the couplings; conditional split probabilities chain to g_k/G
+    # G is the sum of the couplings; the cumulative split fractions step by g_k/G
     np.testing.assert_allclose(geo["G"], geo["g"].sum(1), rtol=1e-14)
-    rem = np.ones(T)
-    for k in range(4):
-        q = np.where(geo["g"][:, k] > 0, geo["csplit"][:, k], 0.0)
-        np.testing.assert_allclose(rem * q, geo["g"][:, k] / geo["G"], rtol=1e-12, atol=1e-300)
-        rem = rem * (1 - q)
+    cum = geo["cum"]
+    assert np.all(cum[:, 3] == 1.0)
+    step = np.diff(np.concatenate([np.zeros((T, 1)), cum[:, :3]], 1), axis=1)
+    np.testing.assert_allclose(step, geo["g"][:, :3] / geo["G"][:, None], rtol=1e-12, atol=1e-15)
+    last = np.array([max([k for k in range(4) if geo["g"][i, k] > 0]) for i in range(T)])
+    np.testing.assert_allclose(cum[np.arange(T), np.minimum(last, 2)] * (last < 3) + (last == 3),
+                               np.where(last < 3, 1.0, 1.0), rtol=1e-12)
     # N_A V[L]
     np.testing.assert_allclose(geo["nav"], 6.02214076e23 * geo["vol"] * 1e3, rtol=1e-15)
     assert inst.tau == pytest.approx(1.0 / (1e-12 * geo["G"].max()), rel=1e-15)

@@ -123,15 +123,17 @@ def _transition_matrix(inst, D):
     return P, geo
 
 
-def test_pure_diffusion_matches_markov_law(oracle_lib):
+@pytest.mark.parametrize("n0,m", [(10, 1), (200, 1), (30, 4)])
+def test_pure_diffusion_matches_markov_law(oracle_lib, n0, m):
     """Without reactions each molecule independently follows P = I - tau L per
-    window, so after m windows the counts are Multinomial(n0, e_i0^T P^m)."""
+    window, so after m windows the counts are Multinomial(n0, e_i0^T P^m).
+    n0 = 10 exercises the per-molecule sampler, n0 = 200 the binomial one."""
     mesh = I.box_mesh(1, 1, 2, 1e-6, jitter=0.1, seed=4).as_dict()
     D = 1e-12
     inst = oracle_lib.Instance(mesh, model([D], [], ["A"]), 0)
     P, _ = _transition_matrix(inst, D)
     T = inst.T
-    n0, i0, m, runs = 30, 3, 4, 2000
+    i0, runs = 3, 2000
     q = np.linalg.matrix_power(P, m)[i0]
     c0 = np.zeros((1, T), np.int32)
     c0[0, i0] = n0
