@@ -25,16 +25,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_02258_amd", "csrc", "rdx_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "window_fast_kernel_simple10_counters.txt")
 
 
-def algorithmic_bytes(T: int, S: int, n_regions: int, molecules_moved: int) -> float:
-    """Bytes one window must move: counts read + written (8 S per tet), the
-    neighbour ids (16), the couplings G, c0, c1, c2 (32), N_A V (8), the region
-    label when the model has regions (1), and one 4-byte read-modify-write per
-    moved molecule's target count (8 each; moved molecules bound the nonzero
-    face moves from above)."""
+def algorithmic_bytes(T: int, S: int, n_regions: int, molecules_moved: float) -> float:
+    """Bytes the all-tets kernel must move in one window: counts read + written
+    (8 S per tet), the neighbour ids (16), the couplings G, cum0..cum2 (32),
+    N_A V (8), the region label when the model has regions (1), and one 4-byte
+    read-modify-write per moved molecule's target count (8 each; moved
+    molecules bound the nonzero face moves from above)."""
     per_tet = 8 * S + 16 + 32 + 8 + (1 if n_regions > 1 else 0)
     return float(T) * per_tet + 8.0 * molecules_moved
+
+
+def measured_traffic():
+    """HBM bytes per launch of the all-tets kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
+    calibration factor), or None if the kernel source changed since."""
+    import hashlib
+    try:
+        kv = dict(line.split(":", 1) for line in open(COUNTERS) if ":" in line and not line.startswith("#"))
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        fetch = float(kv["FETCH_SIZE_KiB_per_dispatch"]) * float(kv["fetch_factor"])
+        write = float(kv["WRITE_SIZE_KiB_per_dispatch"]) * float(kv["write_factor"])
+        return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(workload, seconds: float = 12.0) -> dict:
@@ -94,32 +114,32 @@ def main() -> int:
         one_step()
     torch.cuda.synchronize()
 
-    # timed region: K steps; HIP events on the launch stream bracket the window
-    # launches of every step (the count reset before them is outside the pair)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    events_total = 0
-    moves_total = 0
+    # timed region: K steps.  The library records HIP events on the launch
+    # stream around each window's two kernels (all-tets kernel, SSA event
+    # kernel), which gives each kernel's average duration.
+    sim.kernel_times(reset=True)
+    sim.set_kernel_timing(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
         sim.set_counts(counts0, stream=stream)
-        ev[k][0].record(stream)
         sim.run(w.t_end, stream=stream)
-        ev[k][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    kt = sim.kernel_times(reset=True)
+    sim.set_kernel_timing(False)
     # tallies of the last step (each step restarts from the same counts)
     st = sim.stats(stream)
     windows_per_step = st.windows
     events_total = st.ssa_events * args.steps
     moves_total = st.moves * args.steps
-    kernel_ms = sum(a.elapsed_time(b) for a, b in ev)
-    launches = windows_per_step * args.steps
-    avg_launch_s = max(kernel_ms, 1e-6) * 1e-3 / launches
+    launches = kt["windows"]
+    avg_launch_s = kt["all_tets_ms"] * 1e-3 / max(launches, 1)
+    avg_event_s = kt["event_ms"] * 1e-3 / max(launches, 1)
     voxel_steps = T * windows_per_step * args.steps
     bytes_per_launch = algorithmic_bytes(T, S, n_regions, st.moves / windows_per_step)
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic()
 
     out = {
         "metric": "voxel-steps/s & SSA events/s at 1 GPU; batched p50/p99 latency vs plain",
@@ -142,9 +162,11 @@ def main() -> int:
         "moves_per_s": moves_total / elapsed,
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "window_kernel", "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_launch": bytes_per_launch},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "window_fast_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch,
+                     "event_kernel_avg_us": avg_event_s * 1e6,
+                     "window_us": elapsed * 1e6 / (windows_per_step * args.steps)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -152,6 +152,22 @@ rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, doub
                               int32_t* nbr, double* g, double* G, double* cum, double* nav,
                               double* tau);
 
+/* Per-kernel device time, measured with HIP events recorded on the launch
+ * stream around every window's two kernels (the all-tets kernel and the SSA
+ * event kernel) while timing is enabled.  Timing adds three event records per
+ * window; it is off by default. */
+typedef struct rdx_kernel_times {
+  int64_t windows;        /* windows timed since the last reset */
+  double all_tets_ms;     /* summed duration of the all-tets kernel */
+  double event_ms;        /* summed duration of the SSA event kernel */
+} rdx_kernel_times;
+
+rdx_status rdx_set_kernel_timing(rdx_sim* sim, int enable);
+
+/* Synchronises the stream of the timed windows and returns the sums; with
+ * reset != 0 the sums restart from zero. */
+rdx_status rdx_get_kernel_times(rdx_sim* sim, rdx_kernel_times* out, int reset);
+
 /* Checkpoint: counts, t, window index and tallies.  With buf == NULL, *len
  * receives the required size.  Resume is bit-identical because every draw is
  * addressed by the window index. */
@@ -176,6 +192,12 @@ rdx_status rdx_selftest_ln(const double* x, double* y, int64_t n);
  * (seed, stream_id, tet = j, window), exactly as the diffusion step draws. */
 rdx_status rdx_selftest_binom(uint64_t seed, uint32_t stream_id, uint32_t window, int64_t m,
                               double p, int64_t n, int64_t* out);
+
+/* A plain device-to-device copy of `bytes` bytes (16-byte vector loads and
+ * stores, grid-stride), launched `reps` times after one warm-up; *gbps
+ * receives (read + write bytes) / time.  Calibrates hardware byte counters
+ * and measures the attainable copy bandwidth. */
+rdx_status rdx_selftest_copy(int64_t bytes, int32_t reps, double* gbps);
 
 #ifdef __cplusplus
 }

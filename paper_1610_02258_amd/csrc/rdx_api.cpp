@@ -47,8 +47,17 @@ struct rdx_sim {
   int* err = nullptr;
   int32_t* wl_tet = nullptr;    // [T] tets with an SSA event in the current window
   int32_t* wl_cnt = nullptr;    // [S][T] their counts at the window start
+  double* wl_nav = nullptr;     // [T] their N_A V[L]
+  int32_t* wl_nbr = nullptr;    // [T][4] their neighbours
+  double* wl_geo = nullptr;     // [T][4] their couplings
   int32_t* wl_count = nullptr;  // [2] list lengths, alternating by window parity
   KModel km;
+  // per-kernel timing: three events per window, recycled after each read
+  bool timing = false;
+  std::vector<hipEvent_t> marks;
+  size_t marks_used = 0;
+  int64_t timed_windows = 0;
+  double fast_ms = 0.0, event_ms = 0.0;
   double t = 0.0;
   int64_t window = 0;
   int64_t windows_run = 0;
@@ -71,6 +80,8 @@ hipError_t dev_alloc(T** p, size_t count) {
 }
 
 void free_device(rdx_sim* s) {
+  for (hipEvent_t e : s->marks) (void)hipEventDestroy(e);
+  s->marks.clear();
   (void)hipFree(s->cnt[0]);
   (void)hipFree(s->cnt[1]);
   (void)hipFree(s->nbr);
@@ -83,6 +94,9 @@ void free_device(rdx_sim* s) {
   (void)hipFree(s->wl_tet);
   (void)hipFree(s->wl_cnt);
   (void)hipFree(s->wl_count);
+  (void)hipFree(s->wl_nav);
+  (void)hipFree(s->wl_nbr);
+  (void)hipFree(s->wl_geo);
 }
 
 DevModel make_dev_model(const HostInstance& I) {
@@ -149,11 +163,24 @@ rdx_status launch_one(rdx_sim* s, double tau_k, hipStream_t stream) {
   for (int sp = 0; sp < I.S; ++sp) a.tauD[sp] = tau_k * I.D[sp];
   a.wl_tet = s->wl_tet;
   a.wl_cnt = s->wl_cnt;
+  a.wl_nav = s->wl_nav;
+  a.wl_nbr = s->wl_nbr;
+  a.wl_geo = s->wl_geo;
   a.wl_count = s->wl_count + (s->window & 1);
   a.wl_reset = s->wl_count + ((s->window + 1) & 1);
   a.event_blocks = std::max(1, std::min((I.T + 63) / 64, 1024));
   a.km = s->km;
-  hipError_t e = launch_window(a, stream);
+  hipEvent_t* marks = nullptr;
+  if (s->timing) {
+    while (s->marks.size() < s->marks_used + 3) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return set_error(RDX_EHIP, "hipEventCreate failed");
+      s->marks.push_back(ev);
+    }
+    marks = s->marks.data() + s->marks_used;
+    s->marks_used += 3;
+  }
+  hipError_t e = launch_window(a, stream, marks);
   if (e != hipSuccess) return set_error(RDX_EHIP, std::string("window launch: ") + hipGetErrorString(e));
   s->cur = 1 - s->cur;
   s->window += 1;
@@ -205,7 +232,9 @@ rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t see
             dev_alloc(&s->nav, T) == hipSuccess && dev_alloc(&s->region, T) == hipSuccess &&
             dev_alloc(&s->model, 1) == hipSuccess && dev_alloc(&s->tally, 2) == hipSuccess &&
             dev_alloc(&s->err, 1) == hipSuccess && dev_alloc(&s->wl_tet, T) == hipSuccess &&
-            dev_alloc(&s->wl_cnt, S * T) == hipSuccess && dev_alloc(&s->wl_count, 2) == hipSuccess;
+            dev_alloc(&s->wl_cnt, S * T) == hipSuccess && dev_alloc(&s->wl_count, 2) == hipSuccess &&
+            dev_alloc(&s->wl_nav, T) == hipSuccess && dev_alloc(&s->wl_nbr, 4 * T) == hipSuccess &&
+            dev_alloc(&s->wl_geo, 4 * T) == hipSuccess;
   if (!ok) {
     free_device(s);
     delete s;
@@ -373,6 +402,37 @@ rdx_status rdx_get_geometry(const rdx_sim* s, int32_t* nbr, double* g, double* G
   return RDX_OK;
 }
 
+rdx_status rdx_set_kernel_timing(rdx_sim* s, int enable) {
+  clear_error();
+  if (check_sim(s) != RDX_OK) return RDX_EINVAL;
+  s->timing = enable != 0;
+  return RDX_OK;
+}
+
+rdx_status rdx_get_kernel_times(rdx_sim* s, rdx_kernel_times* out, int reset) {
+  clear_error();
+  if (check_sim(s) != RDX_OK || !out) return set_error(RDX_EINVAL, "null argument");
+  (void)hipSetDevice(s->device);
+  for (size_t k = 0; k + 3 <= s->marks_used; k += 3) {
+    RDX_HIP(hipEventSynchronize(s->marks[k + 2]));
+    float a = 0.f, b = 0.f;
+    RDX_HIP(hipEventElapsedTime(&a, s->marks[k], s->marks[k + 1]));
+    RDX_HIP(hipEventElapsedTime(&b, s->marks[k + 1], s->marks[k + 2]));
+    s->fast_ms += a;
+    s->event_ms += b;
+    s->timed_windows += 1;
+  }
+  s->marks_used = 0;
+  out->windows = s->timed_windows;
+  out->all_tets_ms = s->fast_ms;
+  out->event_ms = s->event_ms;
+  if (reset) {
+    s->timed_windows = 0;
+    s->fast_ms = s->event_ms = 0.0;
+  }
+  return RDX_OK;
+}
+
 rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, double tau_override,
                               int32_t* nbr, double* g, double* G, double* cum, double* nav,
                               double* tau) {
@@ -503,6 +563,36 @@ rdx_status rdx_selftest_binom(uint64_t seed, uint32_t stream_id, uint32_t window
   if (e == hipSuccess) e = hipMemcpy(out, d, sizeof(long long) * n, hipMemcpyDeviceToHost);
   (void)hipFree(d);
   if (e != hipSuccess) return set_error(RDX_EHIP, hipGetErrorString(e));
+  return RDX_OK;
+}
+
+rdx_status rdx_selftest_copy(int64_t bytes, int32_t reps, double* gbps) {
+  clear_error();
+  if (bytes < 16 || reps < 1 || !gbps) return set_error(RDX_EINVAL, "bad arguments");
+  const int64_t n16 = bytes / 16;
+  int4 *a = nullptr, *b = nullptr;
+  RDX_HIP(hipMalloc(&a, sizeof(int4) * n16));
+  if (hipMalloc(&b, sizeof(int4) * n16) != hipSuccess) {
+    (void)hipFree(a);
+    return set_error(RDX_ENOMEM, "device allocation failed");
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMemset(a, 1, sizeof(int4) * n16);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_copy(a, b, n16, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(a, b, n16, nullptr);
+  if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  if (e != hipSuccess) return set_error(RDX_EHIP, hipGetErrorString(e));
+  *gbps = 2.0 * 16.0 * (double)n16 * reps / (ms * 1e-3) / 1e9;
   return RDX_OK;
 }
 

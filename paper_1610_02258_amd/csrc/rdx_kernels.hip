@@ -386,6 +386,8 @@ __device__ __forceinline__ ItemMoves sample_item(const WindowArgs& A, int ti, in
 // Tile schedule of a persistent block: the blocks are dispatched round-robin
 // over the 8 XCDs, so XCD x (= block % 8) owns one contiguous range of tiles
 // (its L2 then sees neighbouring tets), shared round-robin by its blocks.
+// The schedule is static: per-tile work is balanced by the grid size (every
+// block gets the same number of tiles, to within one).
 struct TileRange {
   int first, end, stride;
 };
@@ -500,13 +502,18 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const WindowArgs A) 
     };
     const double a0 = A.region ? sum_propensities(std::true_type{}) : sum_propensities(std::false_type{});
 
-    // first waiting time: does an event fall inside the window?
+    // first waiting time: does an event fall inside the window?  Since
+    // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
+    // margin, far above the rounding of ln and of the division) certainly
+    // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
     bool event = false;
     if (active && a0 > 0.0) {
       Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
       const double u = st.oc();
-      const double t_reac = -ln_basic(u) / a0;
-      event = !(0.0 + t_reac > A.tau_k);
+      if (!(1.0 - u > (A.tau_k * a0) * 1.0000001)) {
+        const double t_reac = -ln_basic(u) / a0;
+        event = !(0.0 + t_reac > A.tau_k);
+      }
     }
     const unsigned long long ballot = __ballot(event);
     if (ballot) {
@@ -515,6 +522,10 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const WindowArgs A) 
       slot = __shfl(slot, 0) + (int)__popcll(ballot & ((1ull << lane) - 1ull));
       if (event) {
         A.wl_tet[slot] = i;
+        A.wl_nav[slot] = nav;
+        reinterpret_cast<int4*>(A.wl_nbr)[slot] = cur.nb;
+        reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = cur.ga;
+        reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = cur.gb;
 #pragma unroll
         for (int s = 0; s < SMAX; ++s)
           if (s < S) A.wl_cnt[(size_t)s * T + slot] = cur.N[s];
@@ -610,33 +621,46 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
   if ((int)blockIdx.x * kWave >= n_work) return;      // whole block idle
 
   const DevModel* __restrict__ M = A.model;
-  for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
-    s_kc[x / RMAX][x % RMAX] = M->kcst[x / RMAX][x % RMAX];
-  for (int x = lane; x < RMAX * SMAX; x += kWave)
-    s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
-  for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
-  if (lane < SMAX) s_tauD[lane] = A.tauD[lane];
-  __syncthreads();
-
   const int T = A.T, S = A.S, R = A.R;
   const double tau = A.tau_k;
   unsigned long long n_ev = 0, n_moved = 0;
   int errbits = 0;
+  bool tables = false;
 
   for (int e0 = blockIdx.x * kWave; e0 < n_work; e0 += gridDim.x * kWave) {
+    // the entry holds everything the tet needs: one round of loads
     const int e = e0 + lane;
     const bool active = e < n_work;
-    const int i = active ? A.wl_tet[e] : 0;
+    int i = 0, reg = 0;
+    int N[SMAX];
+    double nav = 1.0;
+    int4 nb = make_int4(-1, -1, -1, -1);
+    double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * T + e] : 0;
+    if (active) {
+      i = A.wl_tet[e];
+      nav = A.wl_nav[e];
+      nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
+      ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
+      gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
+    }
+    if (!tables) {  // model tables into LDS while the entry loads are in flight
+      for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
+        s_kc[x / RMAX][x % RMAX] = M->kcst[x / RMAX][x % RMAX];
+      for (int x = lane; x < RMAX * SMAX; x += kWave)
+        s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
+      for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
+      if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? A.tauD[s] : 0.0;
+      }
+      __syncthreads();
+      tables = true;
+    }
+    if (active && A.region) reg = A.region[i];
     uint32_t mask = 0;
     if (active) {
-      int N[SMAX];
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) N[s] = s < S ? A.wl_cnt[(size_t)s * T + e] : 0;
-      const int reg = A.region ? (int)A.region[i] : 0;
-      const double nav = A.nav[i];
-      const int4 nb = reinterpret_cast<const int4*>(A.nbr)[i];
-      const double2* gp = reinterpret_cast<const double2*>(A.geo) + 2 * (size_t)i;  // (G, cum0), (cum1, cum2)
-      const double2 ga = gp[0], gb = gp[1];
       const double inv_nav = 1.0 / nav;
       double a[RMAX];
 #pragma unroll
@@ -653,6 +677,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
       uint32_t touched = 0;
       Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
       double dt = 0.0;
+      unsigned int ev_tet = 0;
       for (;;) {
         double a0 = 0.0;
 #pragma unroll
@@ -681,13 +706,14 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)
           if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
-        ++n_ev;
+        ++ev_tet;
         if (errbits) break;
-        if (n_ev >= (unsigned long long)kEventCap) {
+        if (ev_tet >= (unsigned int)kEventCap) {
           errbits |= kErrEvents;
           break;
         }
       }
+      n_ev += ev_tet;
 
       // ---- mean occupancies; items for the diffusion operator ----
       s_tet[lane] = i;
@@ -775,6 +801,12 @@ __global__ void selftest_binom_kernel(uint32_t key0, uint32_t key1, uint32_t str
   out[j] = binom(m, p, st);
 }
 
+__global__ void copy_kernel(const int4* __restrict__ src, int4* __restrict__ dst, int64_t n16) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n16;
+       j += (int64_t)gridDim.x * blockDim.x)
+    dst[j] = src[j];
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -792,27 +824,34 @@ int fast_grid(int n_tiles) {
         &per_cu, reinterpret_cast<const void*>(&window_fast_kernel<SMAX, RMAX>), kWave, 0);
     return n_cu > 0 && per_cu > 0 ? n_cu * per_cu : 2048;
   }();
-  int g = resident < n_tiles ? resident : n_tiles;
-  if (g >= 8) g &= ~7;
+  // fewest rounds of tiles the resident blocks need, then the fewest blocks
+  // (a multiple of 8) that still finish in that many rounds
+  const int rounds = (n_tiles + resident - 1) / resident;
+  int g = (n_tiles + rounds - 1) / rounds;
+  if (g >= 8) g = (g + 7) & ~7;
+  if (g > resident && resident >= 8) g = resident & ~7;
   return g > 0 ? g : 1;
 }
 
 template <int SMAX, int RMAX>
-hipError_t launch_pair(const WindowArgs& a, hipStream_t stream) {
+hipError_t launch_pair(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks) {
   const int n_tiles = (a.T + kWave - 1) / kWave;
+  if (marks) (void)hipEventRecord(marks[0], stream);
   hipLaunchKernelGGL((window_fast_kernel<SMAX, RMAX>), dim3((unsigned)fast_grid<SMAX, RMAX>(n_tiles)),
                      dim3(kWave), 0, stream, a);
+  if (marks) (void)hipEventRecord(marks[1], stream);
   hipLaunchKernelGGL((window_event_kernel<SMAX, RMAX>), dim3((unsigned)a.event_blocks), dim3(kWave), 0,
                      stream, a);
+  if (marks) (void)hipEventRecord(marks[2], stream);
   return hipGetLastError();
 }
 
-hipError_t launch_window(const WindowArgs& a, hipStream_t stream) {
-  if (a.S <= 4 && a.R <= 4) return launch_pair<4, 4>(a, stream);
-  if (a.S <= 8 && a.R <= 8) return launch_pair<8, 8>(a, stream);
-  if (a.S <= 12 && a.R <= 12) return launch_pair<12, 12>(a, stream);
-  if (a.S <= 16 && a.R <= 24) return launch_pair<16, 24>(a, stream);
-  return launch_pair<16, 32>(a, stream);
+hipError_t launch_window(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks) {
+  if (a.S <= 4 && a.R <= 4) return launch_pair<4, 4>(a, stream, marks);
+  if (a.S <= 8 && a.R <= 8) return launch_pair<8, 8>(a, stream, marks);
+  if (a.S <= 12 && a.R <= 12) return launch_pair<12, 12>(a, stream, marks);
+  if (a.S <= 16 && a.R <= 24) return launch_pair<16, 24>(a, stream, marks);
+  return launch_pair<16, 32>(a, stream, marks);
 }
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
@@ -822,6 +861,11 @@ hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, 
 
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(selftest_ln_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const int4* src, int4* dst, int64_t n16, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(256 * 16), dim3(kBlock), 0, s, src, dst, n16);
   return hipGetLastError();
 }
 

@@ -47,6 +47,9 @@ struct WindowArgs {
   double tauD[16];                 // tau_k * D_s, 0 for immobile species
   int32_t* wl_tet;                 // [T] tets with an SSA event in this window
   int32_t* wl_cnt;                 // [S][T] their counts at the window start (row stride T)
+  double* wl_nav;                  // [T] their N_A V[L]
+  int32_t* wl_nbr;                 // [T][4] their neighbours
+  double* wl_geo;                  // [T][4] their (G, cum0, cum1, cum2)
   int32_t* wl_count;               // length of this window's list (zero on entry)
   int32_t* wl_reset;               // the other list length, zeroed for the next window
   int32_t event_blocks;            // grid of the event kernel
@@ -54,11 +57,13 @@ struct WindowArgs {
 };
 
 // One window: the all-tets kernel, then the event kernel over the tets it
-// listed; the instance is picked by (S, R).  Both are enqueued on `stream`.
-hipError_t launch_window(const WindowArgs& a, hipStream_t stream);
+// listed; the instance is picked by (S, R).  Both are enqueued on `stream`;
+// when `marks` is given, marks[0..2] are recorded before, between and after.
+hipError_t launch_window(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks = nullptr);
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_copy(const int4* src, int4* dst, int64_t n16, hipStream_t s);
 hipError_t launch_selftest_binom(uint64_t seed, uint32_t stream_id, uint32_t window, int64_t m,
                                  double p, int64_t n, long long* out, hipStream_t s);
 

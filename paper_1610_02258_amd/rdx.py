@@ -38,12 +38,15 @@ SIGNATURES = {
     "rdx_setup_geometry": ([_p, _p, C.c_double, _p, _p, _p, _p, _p, C.POINTER(C.c_double)], C.c_int),
     "rdx_save": ([_p, _p, C.POINTER(C.c_size_t), _p], C.c_int),
     "rdx_load": ([_p, _p, C.c_size_t, _p], C.c_int),
+    "rdx_set_kernel_timing": ([_p, C.c_int], C.c_int),
+    "rdx_get_kernel_times": ([_p, _p, C.c_int], C.c_int),
     "rdx_last_error": ([], C.c_char_p),
     "rdx_version": ([], C.c_int32),
     "rdx_selftest_philox": ([_p, _p, C.c_int64], C.c_int),
     "rdx_selftest_ln": ([_p, _p, C.c_int64], C.c_int),
     "rdx_selftest_binom": ([C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_double, C.c_int64,
                             _p], C.c_int),
+    "rdx_selftest_copy": ([C.c_int64, C.c_int32, C.POINTER(C.c_double)], C.c_int),
 }
 
 
@@ -97,6 +100,10 @@ class _Model(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_int64), ("voxel_steps", C.c_int64), ("ssa_events", C.c_int64),
                 ("moves", C.c_int64), ("t", C.c_double), ("window_index", C.c_int64)]
+
+
+class _KernelTimes(C.Structure):
+    _fields_ = [("windows", C.c_int64), ("all_tets_ms", C.c_double), ("event_ms", C.c_double)]
 
 
 @dataclass
@@ -226,6 +233,14 @@ class Sim:
         _check(lib().rdx_get_stats(self._h, C.byref(st), _stream_ptr(stream)), "rdx_get_stats")
         return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index)
 
+    def set_kernel_timing(self, enable: bool):
+        _check(lib().rdx_set_kernel_timing(self._h, int(bool(enable))), "rdx_set_kernel_timing")
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        kt = _KernelTimes()
+        _check(lib().rdx_get_kernel_times(self._h, C.byref(kt), int(bool(reset))), "rdx_get_kernel_times")
+        return dict(windows=kt.windows, all_tets_ms=kt.all_tets_ms, event_ms=kt.event_ms)
+
     def geometry(self) -> dict:
         T = self.T
         out = dict(nbr=np.zeros((T, 4), np.int32), g=np.zeros((T, 4)), G=np.zeros(T),
@@ -265,3 +280,17 @@ def selftest_binom(seed: int, m: int, p: float, n: int, stream_id: int = 1, wind
     out = np.zeros(n, np.int64)
     _check(lib().rdx_selftest_binom(seed, stream_id, window, m, p, n, _np_ptr(out)), "rdx_selftest_binom")
     return out
+
+
+def selftest_copy(nbytes: int, reps: int = 20) -> float:
+    """Device copy bandwidth in GB/s (read + write bytes over time)."""
+    g = C.c_double()
+    _check(lib().rdx_selftest_copy(int(nbytes), int(reps), C.byref(g)), "rdx_selftest_copy")
+    return g.value
+
+
+if __name__ == "__main__":
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "copy":
+        nbytes = int(float(sys.argv[2])) if len(sys.argv) > 2 else 1 << 30
+        print(f"copy {nbytes} B: {selftest_copy(nbytes):.1f} GB/s", flush=True)
