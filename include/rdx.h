@@ -174,10 +174,69 @@ rdx_status rdx_get_kernel_times(rdx_sim* sim, rdx_kernel_times* out, int reset);
 rdx_status rdx_save(rdx_sim* sim, void* buf, size_t* len, void* stream);
 rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
 
+/* Launch shape of the window kernels.  Results never depend on it (every
+ * draw is addressed by (seed, stream, tet, window) and moves are integer
+ * sums), only speed does.
+ *   autotune       1: time the candidate shapes on the next windows run
+ *                  (those windows are real work of the simulation) and keep
+ *                  the fastest; get returns 1 while tuning is under way
+ *   fast_grid_div  all-tets kernel grid = resident grid / this (1, 2 or 4)
+ *   graph_windows  windows per captured HIP graph, replayed as one launch;
+ *                  1 = plain launches (1..256) */
+typedef struct rdx_exec_options {
+  int32_t autotune;
+  int32_t fast_grid_div;
+  int32_t graph_windows;
+} rdx_exec_options;
+
+rdx_status rdx_set_exec_options(rdx_sim* sim, const rdx_exec_options* opts);
+rdx_status rdx_get_exec_options(const rdx_sim* sim, rdx_exec_options* opts);
+
+/* ---- batch: many independent runs advanced by the same launches ----
+ *
+ * Run i is a complete simulation (its own mesh, model parameters, seed,
+ * counts, t and window index), exactly as rdx_create would make it; every run
+ * must share the species/reaction structure (n_species, n_reactions, lhs, rhs)
+ * of run 0, while meshes, diffusion coefficients, rate constants and regions
+ * may differ.  One window launch covers the tiles of every run with a window
+ * to do, so small runs fill the GPU together.  Each run's counts equal those
+ * of the same run alone (rdx_create + the same calls), bit for bit.  Device
+ * memory for all runs is reserved at creation.  The launch shape starts in
+ * autotune mode (see rdx_exec_options).  Calls on one batch must be ordered
+ * by the caller (one stream, or synchronised streams).
+ * Errors of create: as rdx_create, prefixed with the failing run's index;
+ * RDX_EINVAL if a run's structure differs from run 0's. */
+typedef struct rdx_batch rdx_batch;
+
+rdx_status rdx_batch_create(int32_t n_runs, const rdx_mesh* meshes /* [n_runs] */,
+                            const rdx_model* models /* [n_runs] */, const uint64_t* seeds /* [n_runs] */,
+                            const double* tau_overrides /* [n_runs] or NULL */, rdx_batch** out);
+void rdx_batch_destroy(rdx_batch* batch);
+rdx_status rdx_batch_size(const rdx_batch* batch, int32_t* n_runs);
+/* n_tets and tau of run i (either may be NULL). */
+rdx_status rdx_batch_get_run_info(const rdx_batch* batch, int32_t i, int32_t* n_tets, double* tau);
+/* As rdx_set_counts / rdx_get_counts for run i. */
+rdx_status rdx_batch_set_counts(rdx_batch* batch, int32_t i, const int32_t* counts, int is_device_ptr,
+                                void* stream);
+rdx_status rdx_batch_get_counts(rdx_batch* batch, int32_t i, int32_t* out, int is_device_ptr,
+                                void* stream);
+/* Algorithm 1 for every run i from its t to t_end[i] (as rdx_run); the
+ * windows of all runs are enqueued together on `stream`. */
+rdx_status rdx_batch_run(rdx_batch* batch, const double* t_end /* [n_runs] */, void* stream);
+/* n_windows full windows for every run (as rdx_step). */
+rdx_status rdx_batch_step(rdx_batch* batch, int64_t n_windows, void* stream);
+/* Waits for `stream`; reports the first device error flag of any run. */
+rdx_status rdx_batch_sync(rdx_batch* batch, void* stream);
+rdx_status rdx_batch_get_stats(rdx_batch* batch, int32_t i, rdx_stats* stats, void* stream);
+rdx_status rdx_batch_set_exec_options(rdx_batch* batch, const rdx_exec_options* opts);
+rdx_status rdx_batch_get_exec_options(const rdx_batch* batch, rdx_exec_options* opts);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* rdx_last_error(void);
 
-/* ABI version of this header (major * 100 + minor). */
+/* ABI version of this header (major * 100 + minor); the library returns
+ * RDX_ABI_VERSION of the header it was built from. */
+#define RDX_ABI_VERSION 200
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

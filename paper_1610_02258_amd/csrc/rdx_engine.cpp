@@ -1,0 +1,623 @@
+// rdx_engine.cpp -- device arena, run state, the runtime main loop of
+// Algorithm 1 as planned sequences of window launches, HIP-graph replay and
+// online tuning of the launch shape.
+#include "rdx_engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace rdx {
+
+namespace {
+
+constexpr size_t kGranule = 256;
+inline size_t align_up(size_t x) { return (x + kGranule - 1) & ~(kGranule - 1); }
+
+#define RDX_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return set_error(RDX_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <typename T>
+hipError_t dev_alloc(T** p, size_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count ? count : 1));
+}
+
+// The batch step index lives in an int32 on the device; it is brought back
+// near zero (keeping its parity, which selects the worklist counter) before it
+// could pass this.
+constexpr int64_t kStepRebase = int64_t(1) << 30;
+
+}  // namespace
+
+// ------------------------------------------------------------------ arena ----
+DeviceArena::~DeviceArena() {
+  if (base_) (void)hipFree(base_);
+}
+
+hipError_t DeviceArena::reserve(size_t bytes) {
+  bytes = align_up(bytes ? bytes : kGranule);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&base_), bytes);
+  if (e != hipSuccess) {
+    base_ = nullptr;
+    return e;
+  }
+  cap_ = bytes;
+  free_.clear();
+  used_.clear();
+  free_[0] = bytes;
+  used_bytes_ = 0;
+  return hipSuccess;
+}
+
+size_t DeviceArena::alloc(size_t bytes) {
+  bytes = align_up(bytes ? bytes : kGranule);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < bytes) continue;
+    const size_t off = it->first, rest = it->second - bytes;
+    free_.erase(it);
+    if (rest) free_[off + bytes] = rest;
+    used_[off] = bytes;
+    used_bytes_ += bytes;
+    return off;
+  }
+  return SIZE_MAX;
+}
+
+void DeviceArena::release(size_t off) {
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t start = off, size = u->second;
+  used_bytes_ -= size;
+  used_.erase(u);
+  auto next = free_.lower_bound(start);
+  if (next != free_.end() && next->first == start + size) {
+    size += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == start) {
+      start = prev->first;
+      size += prev->second;
+      free_.erase(prev);
+    }
+  }
+  free_[start] = size;
+}
+
+size_t DeviceArena::largest_free() const {
+  size_t m = 0;
+  for (const auto& f : free_) m = std::max(m, f.second);
+  return m;
+}
+
+// ------------------------------------------------------------------ model ----
+DevModel make_dev_model(const HostInstance& I) {
+  DevModel m;
+  std::memset(&m, 0, sizeof m);
+  m.S = I.S;
+  m.R = I.R;
+  const int S = I.S, R = I.R;
+  for (int r = 0; r < R; ++r) {
+    int order = 0, r0 = -1, r1 = -1;
+    for (int s = 0; s < S; ++s) {
+      const int nu = I.lhs[(size_t)r * S + s];
+      order += nu;
+      for (int c = 0; c < nu; ++c) {
+        if (r0 < 0) r0 = s;
+        else r1 = s;
+      }
+      m.delta[r][s] = (int8_t)(I.rhs[(size_t)r * S + s] - nu);
+    }
+    const int b0 = r0 < 0 ? 0xff : r0;
+    const int b1 = (order == 2 && r1 >= 0) ? r1 : 0xff;
+    m.info[r] = order | (b0 << 8) | (b1 << 16);
+  }
+  // deps(r): reactions whose propensity reads a species that r changes
+  for (int r = 0; r < R; ++r) {
+    unsigned long long mask = 0;
+    for (int j = 0; j < R; ++j)
+      for (int s = 0; s < S; ++s)
+        if (m.delta[r][s] != 0 && I.lhs[(size_t)j * S + s] > 0) mask |= 1ull << j;
+    m.deps[r] = mask;
+  }
+  return m;
+}
+
+// ----------------------------------------------------------------- engine ----
+size_t Engine::run_bytes(const HostInstance& I) {
+  const size_t T = (size_t)I.T, S = (size_t)I.S;
+  size_t b = 2 * align_up(4 * S * T) + align_up(16 * T) + align_up(32 * T) + align_up(8 * T);
+  if (I.n_regions > 1) b += align_up(T);
+  b += align_up(sizeof(double) * kMaxRegions * 32) + kGranule;  // rate constants; tallies + flag
+  return b;
+}
+
+size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 4 + 4 * (size_t)S + 8 + 16 + 32; }
+
+Engine::~Engine() {
+  if (staged_) (void)hipEventSynchronize(staged_);
+  free_graphs();
+  if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
+  for (hipEvent_t e : marks_) (void)hipEventDestroy(e);
+  if (staged_) (void)hipEventDestroy(staged_);
+  for (hipEvent_t e : tune_ev_)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipFree(model_);
+  (void)hipFree(d_runs_);
+  (void)hipFree(d_tile_map_);
+  (void)hipFree(d_n_tiles_);
+  (void)hipFree(d_base_);
+  (void)hipFree(wl_run_);
+  (void)hipFree(wl_tet_);
+  (void)hipFree(wl_cnt_);
+  (void)hipFree(wl_nav_);
+  (void)hipFree(wl_nbr_);
+  (void)hipFree(wl_geo_);
+  (void)hipFree(wl_count_);
+  if (h_runs_) (void)hipHostFree(h_runs_);
+  if (h_tile_map_) (void)hipHostFree(h_tile_map_);
+  if (h_n_tiles_) (void)hipHostFree(h_n_tiles_);
+}
+
+void Engine::free_graphs() {
+  for (auto& g : graphs_) (void)hipGraphExecDestroy(g.second);
+  graphs_.clear();
+}
+
+rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_runs, int64_t max_tets) {
+  if (max_runs < 1 || max_tets < 1 || max_tets > (int64_t)INT32_MAX)
+    return set_error(RDX_EINVAL, "engine capacity out of range");
+  S_ = proto.S;
+  R_ = proto.R;
+  model_host_ = make_dev_model(proto);
+  max_runs_ = max_runs;
+  max_tets_ = max_tets;
+  max_tiles_ = (max_tets + 63) / 64 + max_runs;
+  if (max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "too many tiles");
+  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>((max_tets + 63) / 64, 1024));
+  const size_t W = (size_t)max_tets;
+  bool ok = dev_alloc(&model_, 1) == hipSuccess && dev_alloc(&d_runs_, (size_t)max_runs) == hipSuccess &&
+            dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
+            dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
+            dev_alloc(&wl_run_, W) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess &&
+            dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
+            dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess &&
+            dev_alloc(&wl_count_, 2) == hipSuccess;
+  if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
+  if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
+  if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
+  if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_n_tiles_), sizeof(int32_t)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return set_error(RDX_ENOMEM, "device allocation failed");
+  }
+  RDX_HIP(hipEventCreateWithFlags(&staged_, hipEventDisableTiming));
+  RDX_HIP(hipEventCreate(&tune_ev_[0]));
+  RDX_HIP(hipEventCreate(&tune_ev_[1]));
+  RDX_HIP(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
+  RDX_HIP(hipMemcpy(model_, &model_host_, sizeof model_host_, hipMemcpyHostToDevice));
+  RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
+  RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
+  RDX_HIP(hipMemset(wl_count_, 0, 2 * sizeof(int32_t)));
+  RDX_HIP(hipDeviceSynchronize());
+  return RDX_OK;
+}
+
+bool Engine::compatible(const HostInstance& I) const {
+  if (I.S != S_ || I.R != R_) return false;
+  const DevModel m = make_dev_model(I);
+  return std::memcmp(m.info, model_host_.info, sizeof m.info) == 0 &&
+         std::memcmp(m.delta, model_host_.delta, sizeof m.delta) == 0 &&
+         std::memcmp(m.deps, model_host_.deps, sizeof m.deps) == 0;
+}
+
+rdx_status Engine::add_run(Run* r, hipStream_t stream) {
+  const HostInstance& I = r->host;
+  if (!compatible(I)) return set_error(RDX_EINVAL, "run does not share the engine's species/reaction structure");
+  if (resident_runs_ >= max_runs_ || resident_tets_ + I.T > max_tets_)
+    return set_error(RDX_EBUDGET, "engine capacity reached");
+  const size_t need = run_bytes(I);
+  const size_t off = arena_.alloc(need);
+  if (off == SIZE_MAX) return set_error(RDX_EBUDGET, "device arena cannot hold the run now");
+  const size_t T = (size_t)I.T, S = (size_t)I.S;
+  char* p = arena_.base() + off;
+  auto carve = [&p](size_t bytes) {
+    char* q = p;
+    p += align_up(bytes);
+    return q;
+  };
+  r->arena_off = off;
+  r->cnt[0] = reinterpret_cast<int32_t*>(carve(4 * S * T));
+  r->cnt[1] = reinterpret_cast<int32_t*>(carve(4 * S * T));
+  r->nbr = reinterpret_cast<int32_t*>(carve(16 * T));
+  r->geo = reinterpret_cast<double*>(carve(32 * T));
+  r->nav = reinterpret_cast<double*>(carve(8 * T));
+  r->region = I.n_regions > 1 ? reinterpret_cast<uint8_t*>(carve(T)) : nullptr;
+  r->kcst = reinterpret_cast<double*>(carve(sizeof(double) * kMaxRegions * 32));
+  char* misc = carve(kGranule);
+  r->tally = reinterpret_cast<unsigned long long*>(misc);
+  r->err = reinterpret_cast<int32_t*>(misc + 2 * sizeof(unsigned long long));
+
+  // host images of the interleaved couplings and the padded rate table; the
+  // copies are synchronous so the images can go when this returns
+  std::vector<double> geo(4 * T);
+  for (size_t i = 0; i < T; ++i) {
+    geo[4 * i + 0] = I.G[i];
+    geo[4 * i + 1] = I.cum[4 * i + 0];
+    geo[4 * i + 2] = I.cum[4 * i + 1];
+    geo[4 * i + 3] = I.cum[4 * i + 2];
+  }
+  std::vector<double> kc((size_t)kMaxRegions * 32, 0.0);
+  for (int reg = 0; reg < I.n_regions; ++reg)
+    for (int q = 0; q < I.R; ++q) kc[(size_t)reg * 32 + q] = I.kcst[(size_t)reg * I.R + q];
+  hipError_t e = hipMemcpyAsync(r->nbr, I.nbr.data(), 16 * T, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->geo, geo.data(), 32 * T, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->nav, I.nav.data(), 8 * T, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && r->region) e = hipMemcpyAsync(r->region, I.region.data(), T, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(r->kcst, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r->cnt[0], 0, 4 * S * T, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(r->cnt[1], 0, 4 * S * T, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(misc, 0, kGranule, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    arena_.release(off);
+    r->arena_off = SIZE_MAX;
+    return set_error(RDX_EHIP, std::string("run upload: ") + hipGetErrorString(e));
+  }
+  r->t = 0.0;
+  r->window = r->windows_run = r->voxel_steps = 0;
+  resident_runs_ += 1;
+  resident_tets_ += I.T;
+  return RDX_OK;
+}
+
+void Engine::remove_run(Run* r, hipStream_t stream) {
+  if (r->arena_off == SIZE_MAX) return;
+  // the run's memory may only be reused once no launch can still touch it
+  (void)hipStreamSynchronize(stream);
+  arena_.release(r->arena_off);
+  r->arena_off = SIZE_MAX;
+  resident_runs_ -= 1;
+  resident_tets_ -= r->host.T;
+  tile_runs_.clear();  // the device tile map may name the run
+}
+
+rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
+  const size_t n = (size_t)r->host.S * (size_t)r->host.T;
+  RDX_HIP(hipMemsetAsync(r->cnt[(r->window + 1) & 1], 0, sizeof(int32_t) * n, stream));
+  RDX_HIP(hipMemsetAsync(r->tally, 0, 2 * sizeof(unsigned long long), stream));
+  RDX_HIP(hipMemsetAsync(r->err, 0, sizeof(int32_t), stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::upload_counts(Run* r, const int32_t* counts, bool device, hipStream_t stream) {
+  const size_t n = (size_t)r->host.S * (size_t)r->host.T;
+  RDX_HIP(hipMemcpyAsync(r->cnt[r->window & 1], counts, sizeof(int32_t) * n,
+                         device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream));
+  if (!device) RDX_HIP(hipStreamSynchronize(stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::download_counts(const Run* r, int32_t* out, bool device, hipStream_t stream) {
+  const size_t n = (size_t)r->host.S * (size_t)r->host.T;
+  RDX_HIP(hipMemcpyAsync(out, r->cnt[r->window & 1], sizeof(int32_t) * n,
+                         device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
+  if (!device) RDX_HIP(hipStreamSynchronize(stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::plan_until(Run* r, double t_end, int64_t max_windows) {
+  if (!std::isfinite(t_end)) return set_error(RDX_EINVAL, "t_end must be finite");
+  const double tau = r->host.tau;
+  double t = r->t;
+  int64_t steps = 0, full = 0;
+  double tau_last = tau;
+  while (t < t_end && (max_windows < 0 || steps < max_windows)) {
+    if (t + tau > t_end) {  // the last window is cut at t_end
+      tau_last = t_end - t;
+      t = t_end;
+      steps += 1;
+      break;
+    }
+    t = t + tau;
+    steps += 1;
+    full += 1;
+  }
+  if (r->window + steps > (int64_t)0xffffffffLL)
+    return set_error(RDX_EINVAL, "window index exceeds the 32-bit RNG counter field");
+  r->plan_steps = steps;
+  r->plan_full = full;
+  r->plan_tau_last = tau_last;
+  r->plan_t_after = t;
+  return RDX_OK;
+}
+
+rdx_status Engine::plan_steps(Run* r, int64_t n) {
+  if (n < 0) return set_error(RDX_EINVAL, "n_windows < 0");
+  if (r->window + n > (int64_t)0xffffffffLL)
+    return set_error(RDX_EINVAL, "window index exceeds the 32-bit RNG counter field");
+  double t = r->t;
+  for (int64_t k = 0; k < n; ++k) t = t + r->host.tau;
+  r->plan_steps = n;
+  r->plan_full = n;
+  r->plan_tau_last = r->host.tau;
+  r->plan_t_after = t;
+  return RDX_OK;
+}
+
+int Engine::fast_grid_for(int64_t n_tiles, int div) const {
+  const int resident = std::max(8, fast_grid_resident(S_, R_) / std::max(1, div));
+  if (n_tiles < 1) return 1;
+  // fewest rounds of tiles the blocks need, then the fewest blocks (a
+  // multiple of the 8 XCDs) that still finish in that many rounds
+  const int64_t rounds = (n_tiles + resident - 1) / resident;
+  int g = (int)((n_tiles + rounds - 1) / rounds);
+  if (g >= 8) g = (g + 7) & ~7;
+  if (g > resident) g = resident & ~7;
+  return g > 0 ? g : 1;
+}
+
+rdx_status Engine::upload_tables(const std::vector<Run*>& active, int64_t k0, hipStream_t stream,
+                                 int64_t* n_tiles_out) {
+  // the pinned images may still be in flight from the previous sequence
+  RDX_HIP(hipEventSynchronize(staged_));
+  const size_t n = active.size();
+  for (size_t j = 0; j < n; ++j) {
+    const Run* r = active[j];
+    const HostInstance& I = r->host;
+    RunDesc& d = h_runs_[j];
+    std::memset(&d, 0, sizeof d);
+    d.cnt[0] = r->cnt[0];
+    d.cnt[1] = r->cnt[1];
+    d.nbr = r->nbr;
+    d.geo = r->geo;
+    d.nav = r->nav;
+    d.region = r->region;
+    d.kcst = r->kcst;
+    d.tally = r->tally;
+    d.err = r->err;
+    d.T = I.T;
+    d.n_steps = (int32_t)(k0 + r->plan_steps);
+    d.n_full = (int32_t)(k0 + r->plan_full);
+    d.window0 = (uint32_t)((uint64_t)r->window - (uint64_t)k0);
+    d.key0 = (uint32_t)(r->seed & 0xffffffffu);
+    d.key1 = (uint32_t)(r->seed >> 32);
+    d.tau = I.tau;
+    d.tau_last = r->plan_tau_last;
+    for (int s = 0; s < I.S; ++s) d.D[s] = I.D[s];
+  }
+  RDX_HIP(hipMemcpyAsync(d_runs_, h_runs_, sizeof(RunDesc) * n, hipMemcpyHostToDevice, stream));
+  // tile map: rebuilt only when the set of runs changes
+  bool same = tile_runs_.size() == n;
+  for (size_t j = 0; same && j < n; ++j) same = tile_runs_[j] == active[j] && tile_run_T_[j] == active[j]->host.T;
+  int64_t n_tiles = 0;
+  for (const Run* r : active) n_tiles += (r->host.T + 63) / 64;
+  if (n_tiles > max_tiles_) return set_error(RDX_EINVAL, "tile map capacity exceeded");
+  if (!same) {
+    int64_t t = 0;
+    for (size_t j = 0; j < n; ++j)
+      for (int32_t first = 0; first < active[j]->host.T; first += 64) h_tile_map_[t++] = make_int2((int)j, first);
+    RDX_HIP(hipMemcpyAsync(d_tile_map_, h_tile_map_, sizeof(int2) * (size_t)n_tiles, hipMemcpyHostToDevice, stream));
+    tile_runs_.assign(active.begin(), active.end());
+    tile_run_T_.resize(n);
+    for (size_t j = 0; j < n; ++j) tile_run_T_[j] = active[j]->host.T;
+  }
+  *h_n_tiles_ = (int32_t)n_tiles;
+  RDX_HIP(hipMemcpyAsync(d_n_tiles_, h_n_tiles_, sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  *n_tiles_out = n_tiles;
+  RDX_HIP(hipEventRecord(staged_, stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::launch_plain(const StepArgs& a0, int64_t K, hipStream_t stream) {
+  StepArgs a = a0;
+  for (int64_t k = 0; k < K; ++k) {
+    a.k_rel = (int32_t)k;
+    hipEvent_t* marks = nullptr;
+    if (timing_) {
+      while (marks_.size() < marks_used_ + 3) {
+        hipEvent_t ev;
+        RDX_HIP(hipEventCreate(&ev));
+        marks_.push_back(ev);
+      }
+      marks = marks_.data() + marks_used_;
+      marks_used_ += 3;
+    }
+    hipError_t e = launch_window(a, stream, marks);
+    if (e != hipSuccess) return set_error(RDX_EHIP, std::string("window launch: ") + hipGetErrorString(e));
+  }
+  if (K > 0) RDX_HIP(launch_advance_base(d_base_, (int32_t)K, stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t stream) {
+  const int W = shape_.graph_windows;
+  const auto key = std::make_pair(W, a0.fast_grid);
+  auto it = graphs_.find(key);
+  if (it == graphs_.end()) {
+    if (graphs_.size() >= 16) free_graphs();
+    // W windows and the step-base advance, captured once on a private stream
+    StepArgs a = a0;
+    RDX_HIP(hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < W && e == hipSuccess; ++k) {
+      a.k_rel = k;
+      e = launch_window(a, capture_stream_, nullptr);
+    }
+    if (e == hipSuccess) e = launch_advance_base(d_base_, W, capture_stream_);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(capture_stream_, &graph);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return set_error(RDX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    it = graphs_.emplace(key, exec).first;
+  }
+  for (int64_t r = 0; r < reps; ++r) RDX_HIP(hipGraphLaunch(it->second, stream));
+  return RDX_OK;
+}
+
+void Engine::set_autotune(bool on) {
+  tuning_ = on;
+  candidates_.clear();
+  cand_ms_.clear();
+  cand_next_ = 0;
+  if (!on) return;
+  // the first entry is a warm-up of the default shape and is not scored
+  candidates_ = {ExecShape{1, 1}, ExecShape{1, 1}, ExecShape{2, 1}, ExecShape{1, 8}, ExecShape{2, 8},
+                 ExecShape{4, 8}};
+}
+
+rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
+  std::vector<Run*> active;
+  int64_t K = 0;
+  for (Run* r : runs)
+    if (r->plan_steps > 0) {
+      if (r->arena_off == SIZE_MAX) return set_error(RDX_ESTATE, "run is not resident");
+      active.push_back(r);
+      K = std::max(K, r->plan_steps);
+    }
+  if (active.empty()) return RDX_OK;
+  if ((int)active.size() > max_runs_) return set_error(RDX_EINVAL, "too many runs in one sequence");
+
+  int64_t k0 = k_now_;
+  if (k0 + K >= kStepRebase) {
+    if (K >= kStepRebase) return set_error(RDX_EINVAL, "sequence too long");
+    k0 = k_now_ & 1;  // keep the parity of the worklist counters
+    RDX_HIP(launch_set_base(d_base_, (int32_t)k0, stream));
+  }
+  int64_t n_tiles = 0;
+  rdx_status st = upload_tables(active, k0, stream, &n_tiles);
+  if (st != RDX_OK) return st;
+
+  StepArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.runs = d_runs_;
+  a.tile_map = d_tile_map_;
+  a.n_tiles = d_n_tiles_;
+  a.step_base = d_base_;
+  a.S = S_;
+  a.R = R_;
+  a.event_blocks = event_blocks_;
+  a.wl_stride = (int32_t)max_tets_;
+  a.model = model_;
+  std::memcpy(a.info, model_host_.info, sizeof a.info);
+  a.wl_run = wl_run_;
+  a.wl_tet = wl_tet_;
+  a.wl_cnt = wl_cnt_;
+  a.wl_nav = wl_nav_;
+  a.wl_nbr = wl_nbr_;
+  a.wl_geo = wl_geo_;
+  a.wl_count = wl_count_;
+
+  auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
+    a.fast_grid = fast_grid_for(n_tiles, sh.fast_grid_div);
+    const ExecShape keep = shape_;
+    shape_ = sh;
+    rdx_status r = RDX_OK;
+    if (!timing_ && sh.graph_windows > 1 && n >= sh.graph_windows) {
+      const int64_t reps = n / sh.graph_windows;
+      r = launch_graphs(a, reps, stream);
+      if (r == RDX_OK) r = launch_plain(a, n - reps * sh.graph_windows, stream);
+    } else {
+      r = launch_plain(a, n, stream);
+    }
+    shape_ = keep;
+    return r;
+  };
+
+  int64_t done = 0;
+  while (tuning_ && !timing_ && done < K && cand_next_ < candidates_.size()) {
+    const ExecShape c = candidates_[cand_next_];
+    const int64_t n = std::min<int64_t>(K - done, std::max(8, 2 * c.graph_windows));
+    if (c.graph_windows > 1 && n >= c.graph_windows) {  // capture outside the timed span
+      a.fast_grid = fast_grid_for(n_tiles, c.fast_grid_div);
+      const ExecShape keep = shape_;
+      shape_ = c;
+      st = launch_graphs(a, 0, stream);
+      shape_ = keep;
+      if (st != RDX_OK) return st;
+    }
+    RDX_HIP(hipEventRecord(tune_ev_[0], stream));
+    st = run_chunk(c, n);
+    if (st != RDX_OK) return st;
+    RDX_HIP(hipEventRecord(tune_ev_[1], stream));
+    RDX_HIP(hipEventSynchronize(tune_ev_[1]));
+    float ms = 0.f;
+    RDX_HIP(hipEventElapsedTime(&ms, tune_ev_[0], tune_ev_[1]));
+    if (cand_next_ > 0) {
+      const double per = (double)ms / (double)n;
+      auto f = cand_ms_.find(c);
+      cand_ms_[c] = f == cand_ms_.end() ? per : std::min(f->second, per);
+    }
+    done += n;
+    cand_next_ += 1;
+    if (cand_next_ == candidates_.size()) {
+      ExecShape best = candidates_[0];
+      double best_ms = 1e300;
+      for (const auto& kv : cand_ms_)
+        if (kv.second < best_ms) {
+          best_ms = kv.second;
+          best = kv.first;
+        }
+      shape_ = best;
+      tuning_ = false;
+    }
+  }
+  if (done < K) {
+    st = run_chunk(shape_, K - done);
+    if (st != RDX_OK) return st;
+  }
+  k_now_ = k0 + K;
+
+  for (Run* r : active) {
+    r->t = r->plan_t_after;
+    r->window += r->plan_steps;
+    r->windows_run += r->plan_steps;
+    r->voxel_steps += r->plan_steps * (int64_t)r->host.T;
+    r->plan_steps = r->plan_full = 0;
+  }
+  return RDX_OK;
+}
+
+rdx_status Engine::kernel_times(rdx_kernel_times* out, bool reset) {
+  for (size_t k = 0; k + 3 <= marks_used_; k += 3) {
+    RDX_HIP(hipEventSynchronize(marks_[k + 2]));
+    float a = 0.f, b = 0.f;
+    RDX_HIP(hipEventElapsedTime(&a, marks_[k], marks_[k + 1]));
+    RDX_HIP(hipEventElapsedTime(&b, marks_[k + 1], marks_[k + 2]));
+    fast_ms_ += a;
+    event_ms_ += b;
+    timed_windows_ += 1;
+  }
+  marks_used_ = 0;
+  out->windows = timed_windows_;
+  out->all_tets_ms = fast_ms_;
+  out->event_ms = event_ms_;
+  if (reset) {
+    timed_windows_ = 0;
+    fast_ms_ = event_ms_ = 0.0;
+  }
+  return RDX_OK;
+}
+
+rdx_status Engine::run_error(const Run* r) const {
+  int32_t flags = 0;
+  RDX_HIP(hipMemcpy(&flags, r->err, sizeof flags, hipMemcpyDeviceToHost));
+  if (flags & kErrOverflow) return set_error(RDX_EOVERFLOW, "a molecule count passed 2^30");
+  if (flags & kErrEvents) return set_error(RDX_EEVENTS, "more than 2^22 SSA events in one tet window");
+  return RDX_OK;
+}
+
+rdx_status Engine::run_tally(const Run* r, unsigned long long tal[2]) const {
+  RDX_HIP(hipMemcpy(tal, r->tally, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  return RDX_OK;
+}
+
+}  // namespace rdx

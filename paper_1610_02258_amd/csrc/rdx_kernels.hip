@@ -292,31 +292,26 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   return v;
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
-// contiguous range of tets so that neighbour updates stay in its L2.
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-  const int q = nb >> 3, rem = nb & 7, xcd = b & 7, slot = b >> 3;
-  return (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + slot;
-}
-
 // ------------------------------------------------------- window kernels ----
-// A window is two launches, one wave (64 lanes) per block, one lane per tet.
+// A window of a batch is two launches, one wave (64 lanes) per block, one lane
+// per tet.
 //
-// window_fast_kernel, over all tets: every global load of the tet is issued up
-// front (counts, N_A V, neighbours, couplings); the propensities and their sum
-// a0 use the model tables held in the kernel arguments; the first SSA waiting
-// time is drawn.  A tet whose first event falls inside the window is appended
-// to a worklist with its counts; for every other tet no count changes, the
-// mean occupancy is the count itself, and its diffusion items are sampled
-// here.  window_event_kernel then runs the full SSA (composition-rejection,
-// occupancy) and the diffusion of the listed tets only.  The heavy per-tet SSA
-// state (propensities, occupancy clocks) thus lives only in the small second
-// kernel, and the all-tets kernel keeps a small register footprint.
+// window_fast_kernel, over all tiles of all runs taking part in the step:
+// every global load of a tet is issued up front (counts, N_A V, neighbours,
+// couplings), the next tile's before the current tile is worked on; the
+// propensities and their sum a0 use uniform reaction tables (scalar loads);
+// the first SSA waiting time is drawn.  A tet whose first event falls inside
+// the window is appended to a worklist with its data; for every other tet no
+// count changes, the mean occupancy is the count itself, and its diffusion
+// items are sampled here.  window_event_kernel then runs the full SSA
+// (composition-rejection, occupancy) and the diffusion of the listed tets
+// only, so the heavy per-tet SSA state never weighs on the all-tets pass.
 //
 // Diffusion items: every (tet, species) pair with something to sample becomes
 // an item; a wave-level prefix sum over the lanes' item counts packs them into
-// LDS, and the 64 lanes then walk the packed list, so a wave spends one pass
-// per 64 items instead of one pass per species.
+// LDS, and the 64 lanes then walk the packed list.  Moves into the tile's own
+// tets accumulate in LDS and are flushed once, coalesced; the rest are integer
+// atomics into the next count buffer.
 constexpr int kWave = 64;
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
@@ -343,11 +338,11 @@ struct ItemMoves {
   int n, o0, o1, o2, o3;
 };
 
-__device__ __forceinline__ ItemMoves sample_item(const WindowArgs& A, int ti, int s, double nbar,
-                                                 int npost, int4 nb, double2 ga, double2 gb,
-                                                 double tauDs) {
+__device__ __forceinline__ ItemMoves sample_item(uint32_t key0, uint32_t key1, uint32_t window,
+                                                 int ti, int s, double nbar, int npost, int4 nb,
+                                                 double2 ga, double2 gb, double tauDs) {
   const int last = nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
-  Draw32 sp(A.key0, A.key1, 1u + (uint32_t)s, (uint32_t)ti, A.window);
+  Draw32 sp(key0, key1, 1u + (uint32_t)s, (uint32_t)ti, window);
   sp.prime();
   const double fl = floor(nbar);
   const double frac = nbar - fl;
@@ -401,6 +396,35 @@ __device__ __forceinline__ TileRange tile_range(int b, int G, int n_tiles) {
   return TileRange{lo + j, hi, Gx};
 }
 
+// The run a tile belongs to and what this step is for that run.
+struct TileCtx {
+  const RunDesc* rd;
+  int run;
+  int base;        // first tet of the tile, run-local
+  int T;
+  bool active;     // the run takes part in this step
+  uint32_t window; // run-local window index
+  double tau_k;
+  int32_t* cin;
+  int32_t* cout;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const StepArgs& A, int tile, int k) {
+  const int2 tm = A.tile_map[tile];
+  const RunDesc* rd = A.runs + tm.x;
+  TileCtx c;
+  c.rd = rd;
+  c.run = tm.x;
+  c.base = tm.y;
+  c.T = rd->T;
+  c.active = k < rd->n_steps;
+  c.window = rd->window0 + (uint32_t)k;
+  c.tau_k = k < rd->n_full ? rd->tau : rd->tau_last;
+  c.cin = rd->cnt[c.window & 1u];
+  c.cout = rd->cnt[(c.window + 1u) & 1u];
+  return c;
+}
+
 // Everything one lane reads from global memory for its tet.
 template <int SMAX>
 struct TetData {
@@ -412,260 +436,318 @@ struct TetData {
 };
 
 template <int SMAX>
-__device__ __forceinline__ void load_tet(const WindowArgs& A, int i, TetData<SMAX>& d) {
-  const bool active = i < A.T;
+__device__ __forceinline__ void load_tet(const TileCtx& c, int S, int i, TetData<SMAX>& d) {
+  const bool active = c.active && i < c.T;
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s)
-    d.N[s] = (active && s < A.S) ? A.cnt_in[(size_t)s * A.T + i] : 0;
+  for (int s = 0; s < SMAX; ++s) d.N[s] = (active && s < S) ? c.cin[(size_t)s * c.T + i] : 0;
   d.nav = 1.0;
   d.nb = make_int4(-1, -1, -1, -1);
   d.ga = make_double2(0.0, 0.0);
   d.gb = make_double2(0.0, 0.0);
   d.reg = 0;
   if (active) {
-    d.nav = A.nav[i];
-    d.nb = reinterpret_cast<const int4*>(A.nbr)[i];
-    const double2* gp = reinterpret_cast<const double2*>(A.geo) + 2 * (size_t)i;
+    d.nav = c.rd->nav[i];
+    d.nb = reinterpret_cast<const int4*>(c.rd->nbr)[i];
+    const double2* gp = reinterpret_cast<const double2*>(c.rd->geo) + 2 * (size_t)i;
     d.ga = gp[0];
     d.gb = gp[1];
-    if (A.region) d.reg = A.region[i];
+    if (c.rd->region) d.reg = c.rd->region[i];
   }
+}
+
+__device__ __forceinline__ int step_index(const StepArgs& A) {
+  return (A.step_base ? *A.step_base : 0) + A.k_rel;
 }
 
 // Persistent: each block (one wave) walks its tiles of 64 tets, issuing the
 // loads of the next tile before working on the current one.
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kWave) window_fast_kernel(const WindowArgs A) {
+__global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   __shared__ int s_acc[SMAX][kWave];         // counts (propensities), then next counts of own tets
   __shared__ double s_tauD[SMAX];
   __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
   __shared__ int s_m[SMAX * kWave];          // count of the item's species
   __shared__ int4 s_nbr[kWave];
   __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants when the model has regions
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of a run with regions
 
   const int lane = threadIdx.x;
-  const int T = A.T, S = A.S, R = A.R;
-  if (lane == 0) {
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? A.tauD[s] : 0.0;
-  }
-  if (A.region) {
-    for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
-      s_kc[x / RMAX][x % RMAX] = A.model->kcst[x / RMAX][x % RMAX];
-  }
-  __syncthreads();
-
-  const int n_tiles = (T + kWave - 1) / kWave;
+  const int S = A.S, R = A.R;
+  const int k = step_index(A);
+  const int n_tiles = *A.n_tiles;
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
-  TetData<SMAX> cur, nxt;
-  if (tr.first < tr.end) load_tet<SMAX>(A, tr.first * kWave + lane, cur);
+  int kc_run = -1, tally_run = -1;
   unsigned long long n_moved = 0;
-  int errbits = 0;
+
+  TileCtx cc, nc;
+  TetData<SMAX> cur, nxt;
+  if (tr.first < tr.end) {
+    cc = tile_ctx(A, tr.first, k);
+    load_tet<SMAX>(cc, S, cc.base + lane, cur);
+  }
+  nc = cc;
 
   for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
-    if (tile + tr.stride < tr.end) load_tet<SMAX>(A, (tile + tr.stride) * kWave + lane, nxt);
-    const int base = tile * kWave;
-    const int i = base + lane;
-    const bool active = i < T;
-
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      s_acc[s][lane] = cur.N[s];
-      if (cur.N[s] != 0) A.cnt_in[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
-      if (cur.N[s] > kCountCap) errbits |= kErrOverflow;
+    if (tile + tr.stride < tr.end) {
+      nc = tile_ctx(A, tile + tr.stride, k);
+      load_tet<SMAX>(nc, S, nc.base + lane, nxt);
     }
-
-    // propensities a_r = c_r h_r(N), summed in reaction order; the reaction
-    // table is uniform (kernel arguments, scalar loads).  Two copies of the
-    // loop on the uniform region flag keep each rate-constant load in one
-    // address space (LDS table with regions, kernel arguments without).
-    const double nav = cur.nav;
-    const double inv_nav = 1.0 / nav;
-    const int reg = cur.reg;
-    auto sum_propensities = [&](auto with_regions) {
-      double acc = 0.0;
+    if (cc.active) {
+      const RunDesc* rd = cc.rd;
+      const int T = cc.T;
+      const int i = cc.base + lane;
+      const bool active = i < T;
+      if (cc.run != tally_run) {  // tallies are kept per run
+        const unsigned long long mv = wave_sum(n_moved);
+        if (lane == 0 && tally_run >= 0 && mv) atomicAdd(A.runs[tally_run].tally + 1, mv);
+        tally_run = cc.run;
+        n_moved = 0;
+      }
+      const bool regions = rd->region != nullptr;
+      if (regions && kc_run != cc.run) {
+        for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
+          s_kc[x / RMAX][x % RMAX] = rd->kcst[(x / RMAX) * 32 + (x % RMAX)];
+        kc_run = cc.run;
+      }
+      if (lane == 0) {
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r) {
-        if (r < R) {
-          const int info = A.km.info[r];
-          double k;
-          if constexpr (decltype(with_regions)::value) k = s_kc[reg][r];
-          else k = A.km.kcst0[r];
-          const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-          const int n0 = s0 < SMAX ? s_acc[s0][lane] : 0;
-          const int n1 = s1 < SMAX ? s_acc[s1][lane] : 0;
-          acc = acc + mass_action(info, k, n0, n1, nav, inv_nav);
-        }
+        for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? cc.tau_k * rd->D[s] : 0.0;
       }
-      return acc;
-    };
-    const double a0 = A.region ? sum_propensities(std::true_type{}) : sum_propensities(std::false_type{});
-
-    // first waiting time: does an event fall inside the window?  Since
-    // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
-    // margin, far above the rounding of ln and of the division) certainly
-    // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
-    bool event = false;
-    if (active && a0 > 0.0) {
-      Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
-      const double u = st.oc();
-      if (!(1.0 - u > (A.tau_k * a0) * 1.0000001)) {
-        const double t_reac = -ln_basic(u) / a0;
-        event = !(0.0 + t_reac > A.tau_k);
-      }
-    }
-    const unsigned long long ballot = __ballot(event);
-    if (ballot) {
-      int slot = 0;
-      if (lane == 0) slot = atomicAdd(A.wl_count, (int)__popcll(ballot));
-      slot = __shfl(slot, 0) + (int)__popcll(ballot & ((1ull << lane) - 1ull));
-      if (event) {
-        A.wl_tet[slot] = i;
-        A.wl_nav[slot] = nav;
-        reinterpret_cast<int4*>(A.wl_nbr)[slot] = cur.nb;
-        reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = cur.ga;
-        reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = cur.gb;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s)
-          if (s < S) A.wl_cnt[(size_t)s * T + slot] = cur.N[s];
-      }
-    }
-
-    // no event: Nbar = N; items for the diffusion operator.  The accumulator
-    // starts with what cannot leave (the event kernel handles listed tets).
-    uint32_t mask = 0;
-    s_nbr[lane] = cur.nb;
-    s_geo[0][lane] = cur.ga;
-    s_geo[1][lane] = cur.gb;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      int start = 0;
-      if (active && !event && s < S) {
-        if (A.tauD[s] > 0.0 && cur.ga.x > 0.0 && cur.N[s] > 0) mask |= 1u << s;
-        else start = cur.N[s];
-      }
-      s_acc[s][lane] = start;
-    }
-    const int cnt = __popc(mask);
-    const int incl = wave_inclusive_scan(cnt);
-    const int total = __shfl(incl, kWave - 1);
-    int pos = incl - cnt;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if ((mask >> s) & 1u) {
-        s_item[pos] = (uint16_t)((lane << 4) | s);
-        s_m[pos] = cur.N[s];
-        ++pos;
-      }
-    __syncthreads();
-
-    for (int j = lane; j < total; j += kWave) {
-      const int it = s_item[j];
-      const int L = it >> 4, sp = it & 15;
-      const int m = s_m[j];
-      const int4 tnb = s_nbr[L];
-      const ItemMoves mv = sample_item(A, base + L, sp, (double)m, m, tnb, s_geo[0][L],
-                                       s_geo[1][L], s_tauD[sp]);
-      // own remainder and moves to the tile's own tets go to LDS, the rest
-      // to the next count buffer
-      int32_t* __restrict__ out_s = A.cnt_out + (size_t)sp * T;
-      if (m != mv.n) atomicAdd(&s_acc[sp][L], m - mv.n);
-#define RDX_DEPOSIT(t, v)                                               \
-      if (v) {                                                          \
-        const unsigned off = (unsigned)((t) - base);                     \
-        if (off < (unsigned)kWave) atomicAdd(&s_acc[sp][off], (v));      \
-        else atomicAdd(out_s + (t), (v));                                \
-      }
-      RDX_DEPOSIT(tnb.x, mv.o0)
-      RDX_DEPOSIT(tnb.y, mv.o1)
-      RDX_DEPOSIT(tnb.z, mv.o2)
-      RDX_DEPOSIT(tnb.w, mv.o3)
-#undef RDX_DEPOSIT
-      n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
-    }
-    __syncthreads();
-    // coalesced flush of the tile's own tets (other tiles add into them too)
-    if (active) {
+      int errbits = 0;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) {
-        const int v = s < S ? s_acc[s][lane] : 0;
-        if (v != 0) atomicAdd(A.cnt_out + (size_t)s * T + i, v);
+        s_acc[s][lane] = cur.N[s];
+        if (cur.N[s] != 0) cc.cin[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
+        if (cur.N[s] > kCountCap) errbits |= kErrOverflow;
       }
+      __syncthreads();
+
+      // propensities a_r = c_r h_r(N), summed in reaction order; the reaction
+      // table is uniform (scalar loads).  Two copies of the loop on the uniform
+      // region flag keep each rate-constant load in one address space.
+      const double nav = cur.nav;
+      const double inv_nav = 1.0 / nav;
+      const int reg = cur.reg;
+      auto sum_propensities = [&](auto with_regions) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (r < R) {
+            const int info = A.info[r];
+            double kr;
+            if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
+            else kr = rd->kcst[r];
+            const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+            const int n0 = s0 < SMAX ? s_acc[s0][lane] : 0;
+            const int n1 = s1 < SMAX ? s_acc[s1][lane] : 0;
+            acc = acc + mass_action(info, kr, n0, n1, nav, inv_nav);
+          }
+        }
+        return acc;
+      };
+      const double a0 = regions ? sum_propensities(std::true_type{}) : sum_propensities(std::false_type{});
+
+      // first waiting time: does an event fall inside the window?  Since
+      // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
+      // margin, far above the rounding of ln and of the division) certainly
+      // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
+      bool event = false;
+      if (active && a0 > 0.0) {
+        Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
+        const double u = st.oc();
+        if (!(1.0 - u > (cc.tau_k * a0) * 1.0000001)) {
+          const double t_reac = -ln_basic(u) / a0;
+          event = !(0.0 + t_reac > cc.tau_k);
+        }
+      }
+      const unsigned long long ballot = __ballot(event);
+      if (ballot) {
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(A.wl_count + (k & 1), (int)__popcll(ballot));
+        slot = __shfl(slot, 0) + (int)__popcll(ballot & ((1ull << lane) - 1ull));
+        if (event) {
+          A.wl_run[slot] = cc.run;
+          A.wl_tet[slot] = i;
+          A.wl_nav[slot] = nav;
+          reinterpret_cast<int4*>(A.wl_nbr)[slot] = cur.nb;
+          reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = cur.ga;
+          reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = cur.gb;
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s)
+            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = cur.N[s];
+        }
+      }
+
+      // no event: Nbar = N; items for the diffusion operator.  The accumulator
+      // starts with what cannot leave (the event kernel handles listed tets).
+      uint32_t mask = 0;
+      s_nbr[lane] = cur.nb;
+      s_geo[0][lane] = cur.ga;
+      s_geo[1][lane] = cur.gb;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        int start = 0;
+        if (active && !event && s < S) {
+          if (rd->D[s] > 0.0 && cur.ga.x > 0.0 && cur.N[s] > 0) mask |= 1u << s;
+          else start = cur.N[s];
+        }
+        s_acc[s][lane] = start;
+      }
+      const int cnt = __popc(mask);
+      const int incl = wave_inclusive_scan(cnt);
+      const int total = __shfl(incl, kWave - 1);
+      int pos = incl - cnt;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if ((mask >> s) & 1u) {
+          s_item[pos] = (uint16_t)((lane << 4) | s);
+          s_m[pos] = cur.N[s];
+          ++pos;
+        }
+      __syncthreads();
+
+      const int base = cc.base;
+      for (int j = lane; j < total; j += kWave) {
+        const int it = s_item[j];
+        const int L = it >> 4, sp = it & 15;
+        const int m = s_m[j];
+        const int4 tnb = s_nbr[L];
+        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, base + L, sp, (double)m, m,
+                                         tnb, s_geo[0][L], s_geo[1][L], s_tauD[sp]);
+        // own remainder and moves to the tile's own tets go to LDS, the rest
+        // to the next count buffer
+        int32_t* __restrict__ out_s = cc.cout + (size_t)sp * T;
+        if (m != mv.n) atomicAdd(&s_acc[sp][L], m - mv.n);
+#define RDX_DEPOSIT(t, v)                                               \
+        if (v) {                                                        \
+          const unsigned off = (unsigned)((t) - base);                   \
+          if (off < (unsigned)kWave) atomicAdd(&s_acc[sp][off], (v));    \
+          else atomicAdd(out_s + (t), (v));                              \
+        }
+        RDX_DEPOSIT(tnb.x, mv.o0)
+        RDX_DEPOSIT(tnb.y, mv.o1)
+        RDX_DEPOSIT(tnb.z, mv.o2)
+        RDX_DEPOSIT(tnb.w, mv.o3)
+#undef RDX_DEPOSIT
+        n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+      }
+      __syncthreads();
+      // coalesced flush of the tile's own tets (other tiles add into them too)
+      if (active) {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          const int v = s < S ? s_acc[s][lane] : 0;
+          if (v != 0) atomicAdd(cc.cout + (size_t)s * T + i, v);
+        }
+      }
+      if (errbits) atomicOr(rd->err, errbits);
+      __syncthreads();  // LDS is rebuilt for the next tile
     }
-    __syncthreads();  // LDS is rebuilt for the next tile
+    cc = nc;
     cur = nxt;
   }
 
-  const unsigned long long mv_sum = wave_sum(n_moved);
-  if (lane == 0 && mv_sum) atomicAdd(A.tally + 1, mv_sum);
-  if (errbits) atomicOr(A.err, errbits);
+  const unsigned long long mv = wave_sum(n_moved);
+  if (lane == 0 && tally_run >= 0 && mv) atomicAdd(A.runs[tally_run].tally + 1, mv);
+}
+
+// Adds v (per lane) to field f of each lane's run tally: one atomic per wave
+// when all lanes with something to add belong to the same run.
+__device__ __forceinline__ void add_run_tally(const StepArgs& A, int run, unsigned long long v, int f) {
+  const unsigned long long has = __ballot(v != 0);
+  if (!has) return;
+  const int leader = __ffsll((long long)has) - 1;
+  const int r0 = __shfl(run, leader);
+  if (__all(v == 0 || run == r0)) {
+    const unsigned long long sum = wave_sum(v);
+    if ((int)(threadIdx.x & (kWave - 1)) == leader) atomicAdd(A.runs[r0].tally + f, sum);
+  } else if (v) {
+    atomicAdd(A.runs[run].tally + f, v);
+  }
 }
 
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A) {
-  __shared__ double s_kc[kMaxRegions][RMAX];
+__global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
   __shared__ int8_t s_delta[RMAX][SMAX];
   __shared__ unsigned long long s_deps[RMAX];
-  __shared__ double s_tauD[SMAX];
+  __shared__ double s_k[RMAX][kWave];        // rate constants of the lane's run and region
+  __shared__ double s_td[SMAX][kWave];       // tau_k D_s of the lane's run
   __shared__ double s_nbar[SMAX][kWave];     // mean occupancy of item (lane, s)
   __shared__ int s_npost[SMAX][kWave];       // post-reaction count of item (lane, s)
   __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
   __shared__ int4 s_nbr[kWave];
   __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
   __shared__ int s_tet[kWave];
+  __shared__ int s_run[kWave];
+  __shared__ uint32_t s_win[kWave];
+  __shared__ unsigned long long s_moved[kWave];
 
   const int lane = threadIdx.x;
-  const int n_work = *A.wl_count;
-  if (blockIdx.x == 0 && lane == 0) *A.wl_reset = 0;  // the next window's list starts empty
-  if ((int)blockIdx.x * kWave >= n_work) return;      // whole block idle
+  const int k = step_index(A);
+  const int n_work = A.wl_count[k & 1];
+  if (blockIdx.x == 0 && lane == 0) A.wl_count[(k + 1) & 1] = 0;  // next window's list starts empty
+  if ((int)blockIdx.x * kWave >= n_work) return;                   // whole block idle
 
   const DevModel* __restrict__ M = A.model;
-  const int T = A.T, S = A.S, R = A.R;
-  const double tau = A.tau_k;
-  unsigned long long n_ev = 0, n_moved = 0;
-  int errbits = 0;
+  const int S = A.S, R = A.R;
   bool tables = false;
 
   for (int e0 = blockIdx.x * kWave; e0 < n_work; e0 += gridDim.x * kWave) {
     // the entry holds everything the tet needs: one round of loads
     const int e = e0 + lane;
     const bool active = e < n_work;
-    int i = 0, reg = 0;
+    int run = 0, i = 0;
     int N[SMAX];
     double nav = 1.0;
     int4 nb = make_int4(-1, -1, -1, -1);
     double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s) N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * T + e] : 0;
+    for (int s = 0; s < SMAX; ++s)
+      N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
     if (active) {
+      run = A.wl_run[e];
       i = A.wl_tet[e];
       nav = A.wl_nav[e];
       nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
       ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
       gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
     }
-    if (!tables) {  // model tables into LDS while the entry loads are in flight
-      for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
-        s_kc[x / RMAX][x % RMAX] = M->kcst[x / RMAX][x % RMAX];
+    if (!tables) {  // reaction tables into LDS while the entry loads are in flight
       for (int x = lane; x < RMAX * SMAX; x += kWave)
         s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
       for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
-      if (lane == 0) {
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? A.tauD[s] : 0.0;
-      }
-      __syncthreads();
       tables = true;
     }
-    if (active && A.region) reg = A.region[i];
+    const RunDesc* rd = A.runs + run;
+    uint32_t window = 0, key0 = 0, key1 = 0;
+    double tau = 1.0;
+    int32_t* cout = nullptr;
+    int T = 0;
+    if (active) {
+      window = rd->window0 + (uint32_t)k;
+      tau = k < rd->n_full ? rd->tau : rd->tau_last;
+      key0 = rd->key0;
+      key1 = rd->key1;
+      cout = rd->cnt[(window + 1u) & 1u];
+      T = rd->T;
+      const int reg = rd->region ? (int)rd->region[i] : 0;
+      for (int r = 0; r < RMAX; ++r)
+        if (r < R) s_k[r][lane] = rd->kcst[reg * 32 + r];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) s_td[s][lane] = s < S ? tau * rd->D[s] : 0.0;
+    }
+    s_moved[lane] = 0;
+    __syncthreads();
+
+    unsigned long long n_ev = 0;
+    int errbits = 0;
     uint32_t mask = 0;
     if (active) {
       const double inv_nav = 1.0 / nav;
       double a[RMAX];
 #pragma unroll
       for (int r = 0; r < RMAX; ++r)
-        a[r] = r < R ? propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav) : 0.0;
+        a[r] = r < R ? propensity<SMAX>(M, r, s_k[r][lane], N, nav, inv_nav) : 0.0;
 
       // ---- reaction SSA operator over [0, tau_k] ----
       double O[SMAX], tS[SMAX];
@@ -675,7 +757,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
         tS[s] = 0.0;
       }
       uint32_t touched = 0;
-      Draw53 st(A.key0, A.key1, 0u, (uint32_t)i, A.window);
+      Draw53 st(key0, key1, 0u, (uint32_t)i, window);
       double dt = 0.0;
       unsigned int ev_tet = 0;
       for (;;) {
@@ -705,7 +787,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
         const unsigned long long dep = s_deps[rn];
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)
-          if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
+          if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_k[r][lane], N, nav, inv_nav);
         ++ev_tet;
         if (errbits) break;
         if (ev_tet >= (unsigned int)kEventCap) {
@@ -713,10 +795,12 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
           break;
         }
       }
-      n_ev += ev_tet;
+      n_ev = ev_tet;
 
       // ---- mean occupancies; items for the diffusion operator ----
       s_tet[lane] = i;
+      s_run[lane] = run;
+      s_win[lane] = window;
       s_nbr[lane] = nb;
       s_geo[0][lane] = ga;
       s_geo[1][lane] = gb;
@@ -730,12 +814,12 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
         } else {
           nbar = (double)N[s];
         }
-        if (s_tauD[s] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
+        if (s_td[s][lane] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
           mask |= 1u << s;
           s_nbar[s][lane] = nbar;
           s_npost[s][lane] = N[s];
         } else if (N[s] != 0) {
-          atomicAdd(A.cnt_out + (size_t)s * T + i, N[s]);  // nothing can leave
+          atomicAdd(cout + (size_t)s * T + i, N[s]);  // nothing can leave
         }
       }
     }
@@ -749,31 +833,33 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const WindowArgs A)
     __syncthreads();
     for (int j = lane; j < total; j += kWave) {
       const int it = s_item[j];
-      const int L = it >> 4, s = it & 15;
+      const int L = it >> 4, sp = it & 15;
       const int ti = s_tet[L];
-      const int npost = s_npost[s][L];
+      const int npost = s_npost[sp][L];
       const int4 tnb = s_nbr[L];
-      const ItemMoves mv = sample_item(A, ti, s, s_nbar[s][L], npost, tnb, s_geo[0][L],
-                                       s_geo[1][L], s_tauD[s]);
-      int32_t* out_s = A.cnt_out + (size_t)s * T;
+      const RunDesc* trd = A.runs + s_run[L];
+      const uint32_t twin = s_win[L];
+      const ItemMoves mv = sample_item(trd->key0, trd->key1, twin, ti, sp, s_nbar[sp][L], npost,
+                                       tnb, s_geo[0][L], s_geo[1][L], s_td[sp][L]);
+      int32_t* out_s = trd->cnt[(twin + 1u) & 1u] + (size_t)sp * trd->T;
       if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
       if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
       if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
       if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
       if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
-      n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+      const int moved = mv.o0 + mv.o1 + mv.o2 + mv.o3;
+      if (moved) atomicAdd(&s_moved[L], (unsigned long long)moved);
     }
+    __syncthreads();
+    add_run_tally(A, run, active ? n_ev : 0ull, 0);
+    add_run_tally(A, run, active ? s_moved[lane] : 0ull, 1);
+    if (errbits) atomicOr(rd->err, errbits);
     __syncthreads();  // the LDS item list is rebuilt for the next 64 entries
   }
-
-  const unsigned long long ev_sum = wave_sum(n_ev);
-  const unsigned long long mv_sum = wave_sum(n_moved);
-  if (lane == 0) {
-    if (ev_sum) atomicAdd(A.tally + 0, ev_sum);
-    if (mv_sum) atomicAdd(A.tally + 1, mv_sum);
-  }
-  if (errbits) atomicOr(A.err, errbits);
 }
+
+__global__ void advance_base_kernel(int32_t* base, int32_t add) { *base += add; }
+__global__ void set_base_kernel(int32_t* base, int32_t value) { *base = value; }
 
 // ----------------------------------------------------------- self-tests ----
 __global__ void selftest_philox_kernel(const uint32_t* in, uint32_t* out, int64_t n) {
@@ -811,11 +897,9 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
-// Persistent grid of the all-tets kernel: as many one-wave blocks as the
-// device holds at once (occupancy x compute units), rounded down to a
-// multiple of the 8 XCDs, never more than there are tiles.
+// Blocks of the all-tets kernel the device holds at once (occupancy x CUs).
 template <int SMAX, int RMAX>
-int fast_grid(int n_tiles) {
+int resident_blocks() {
   static const int resident = [] {
     int dev = 0, n_cu = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
@@ -824,21 +908,14 @@ int fast_grid(int n_tiles) {
         &per_cu, reinterpret_cast<const void*>(&window_fast_kernel<SMAX, RMAX>), kWave, 0);
     return n_cu > 0 && per_cu > 0 ? n_cu * per_cu : 2048;
   }();
-  // fewest rounds of tiles the resident blocks need, then the fewest blocks
-  // (a multiple of 8) that still finish in that many rounds
-  const int rounds = (n_tiles + resident - 1) / resident;
-  int g = (n_tiles + rounds - 1) / rounds;
-  if (g >= 8) g = (g + 7) & ~7;
-  if (g > resident && resident >= 8) g = resident & ~7;
-  return g > 0 ? g : 1;
+  return resident;
 }
 
 template <int SMAX, int RMAX>
-hipError_t launch_pair(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks) {
-  const int n_tiles = (a.T + kWave - 1) / kWave;
+hipError_t launch_pair(const StepArgs& a, hipStream_t stream, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[0], stream);
-  hipLaunchKernelGGL((window_fast_kernel<SMAX, RMAX>), dim3((unsigned)fast_grid<SMAX, RMAX>(n_tiles)),
-                     dim3(kWave), 0, stream, a);
+  hipLaunchKernelGGL((window_fast_kernel<SMAX, RMAX>), dim3((unsigned)a.fast_grid), dim3(kWave), 0,
+                     stream, a);
   if (marks) (void)hipEventRecord(marks[1], stream);
   hipLaunchKernelGGL((window_event_kernel<SMAX, RMAX>), dim3((unsigned)a.event_blocks), dim3(kWave), 0,
                      stream, a);
@@ -846,12 +923,30 @@ hipError_t launch_pair(const WindowArgs& a, hipStream_t stream, hipEvent_t* mark
   return hipGetLastError();
 }
 
-hipError_t launch_window(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks) {
+int fast_grid_resident(int S, int R) {
+  if (S <= 4 && R <= 4) return resident_blocks<4, 4>();
+  if (S <= 8 && R <= 8) return resident_blocks<8, 8>();
+  if (S <= 12 && R <= 12) return resident_blocks<12, 12>();
+  if (S <= 16 && R <= 24) return resident_blocks<16, 24>();
+  return resident_blocks<16, 32>();
+}
+
+hipError_t launch_window(const StepArgs& a, hipStream_t stream, hipEvent_t* marks) {
   if (a.S <= 4 && a.R <= 4) return launch_pair<4, 4>(a, stream, marks);
   if (a.S <= 8 && a.R <= 8) return launch_pair<8, 8>(a, stream, marks);
   if (a.S <= 12 && a.R <= 12) return launch_pair<12, 12>(a, stream, marks);
   if (a.S <= 16 && a.R <= 24) return launch_pair<16, 24>(a, stream, marks);
   return launch_pair<16, 32>(a, stream, marks);
+}
+
+hipError_t launch_advance_base(int32_t* base, int32_t add, hipStream_t stream) {
+  hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, stream, base, add);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_base(int32_t* base, int32_t value, hipStream_t stream) {
+  hipLaunchKernelGGL(set_base_kernel, dim3(1), dim3(1), 0, stream, base, value);
+  return hipGetLastError();
 }
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {

@@ -1,4 +1,10 @@
 // rdx_kernels.hpp -- launch interface of the gfx950 kernels (host side).
+//
+// The kernels advance a batch of independent runs (one simulation is a batch
+// of one).  Every run has its own mesh arrays, count buffers, seed, rate
+// constants and window schedule; all runs share the species/reaction
+// structure.  The tets of all runs are cut into tiles of 64 (a tile never
+// spans two runs), and a persistent grid walks the tiles.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -7,59 +13,74 @@
 
 namespace rdx {
 
-// Model tables in the layout the window kernels read (one device copy per sim).
-// info[r] packs reaction r's order (bits 0-7) and reactant species r0, r1
-// (bits 8-15, 16-23; 0xff if absent; r0 == r1 for a homodimer) in one dword so
-// that uniform reads are scalar loads.  delta[r][s] is the net change of
-// species s, deps[r] the reactions whose propensity reads a species r changes.
+// Reaction tables shared by the runs of a batch (one device copy).  info[r]
+// packs reaction r's order (bits 0-7) and reactant species r0, r1 (bits 8-15,
+// 16-23; 0xff if absent; r0 == r1 for a homodimer) in one dword so that
+// uniform reads are scalar loads.  delta[r][s] is the net change of species
+// s, deps[r] the reactions whose propensity reads a species r changes.
 struct alignas(16) DevModel {
-  int32_t S, R, n_regions, pad;
+  int32_t S, R, pad0, pad1;
   int32_t info[32];
   int8_t delta[32][16];
   unsigned long long deps[32];
-  double kcst[8][32];              // [region][reaction]
 };
 
-// The reaction constants the all-tets kernel reads from its kernel arguments:
-// packed reaction info and the rate constants of region 0 (models with several
-// regions read DevModel::kcst per tet).
-struct alignas(16) KModel {
-  int32_t info[32];
-  double kcst0[32];
-};
-
-// Arguments of one window over one simulation.
-struct WindowArgs {
-  int32_t* cnt_in;                 // [S][T] counts at the window start; zeroed as they are read
-  int32_t* cnt_out;                // [S][T] all zero on entry; receives the counts after the window
-  const int32_t* nbr;              // [T][4] int4 per tet
-  const double* geo;               // [T][4] (G, cum0, cum1, cum2) double4 per tet
-  const double* nav;               // [T]
-  const uint8_t* region;           // [T] or nullptr
-  const DevModel* model;
-  unsigned long long* tally;       // [2] SSA events, molecules moved
-  int* err;                        // error-flag bits
+// One run of the batch, as the kernels read it (device memory).
+struct alignas(16) RunDesc {
+  int32_t* cnt[2];             // [S][T] count buffers; window w reads cnt[w & 1], writes cnt[(w + 1) & 1]
+  const int32_t* nbr;          // [T][4] neighbours (-1 = boundary)
+  const double* geo;           // [T][4] (G, cum0, cum1, cum2)
+  const double* nav;           // [T] N_A V[L]
+  const uint8_t* region;       // [T] region labels, nullptr when the model has one region
+  const double* kcst;          // [8][32] rate constants by region
+  unsigned long long* tally;   // [2] SSA events, molecules moved
+  int32_t* err;                // error-flag bits
   int32_t T;
-  int32_t S, R;
-  uint32_t key0, key1;
-  uint32_t window;
-  double tau_k;
-  double tauD[16];                 // tau_k * D_s, 0 for immobile species
-  int32_t* wl_tet;                 // [T] tets with an SSA event in this window
-  int32_t* wl_cnt;                 // [S][T] their counts at the window start (row stride T)
-  double* wl_nav;                  // [T] their N_A V[L]
-  int32_t* wl_nbr;                 // [T][4] their neighbours
-  double* wl_geo;                  // [T][4] their (G, cum0, cum1, cum2)
-  int32_t* wl_count;               // length of this window's list (zero on entry)
-  int32_t* wl_reset;               // the other list length, zeroed for the next window
-  int32_t event_blocks;            // grid of the event kernel
-  KModel km;
+  int32_t n_steps;             // windows of the current sequence (steps 0 .. n_steps-1)
+  int32_t n_full;              // steps < n_full last tau, step n_full (if < n_steps) tau_last
+  uint32_t window0;            // run-local window index of step 0
+  uint32_t key0, key1;         // Philox key = seed
+  double tau, tau_last;
+  double D[16];                // diffusion coefficients
 };
+
+// Arguments of one window of a batch (identical for every window of a
+// sequence except k_rel).
+struct StepArgs {
+  const RunDesc* runs;
+  const int2* tile_map;        // [n_tiles] (run, first tet of the tile within the run)
+  const int32_t* n_tiles;      // device: number of tiles
+  const int32_t* step_base;    // device: step index of k_rel = 0 (nullptr: 0)
+  int32_t k_rel;
+  int32_t S, R;
+  int32_t fast_grid;           // persistent grid of the all-tets kernel
+  int32_t event_blocks;        // grid of the event kernel
+  int32_t wl_stride;           // worklist capacity (row stride of wl_cnt)
+  const DevModel* model;
+  int32_t info[32];            // = model->info, in kernel arguments for scalar loads
+  // worklist of the tets whose first SSA event falls inside the window
+  int32_t* wl_run;
+  int32_t* wl_tet;
+  int32_t* wl_cnt;             // [S][wl_stride]
+  double* wl_nav;
+  int32_t* wl_nbr;             // [wl_stride][4]
+  double* wl_geo;              // [wl_stride][4]
+  int32_t* wl_count;           // [2] list lengths by step parity
+};
+
+// Resident-grid size of the all-tets kernel for (S, R): occupancy x compute units.
+int fast_grid_resident(int S, int R);
 
 // One window: the all-tets kernel, then the event kernel over the tets it
 // listed; the instance is picked by (S, R).  Both are enqueued on `stream`;
 // when `marks` is given, marks[0..2] are recorded before, between and after.
-hipError_t launch_window(const WindowArgs& a, hipStream_t stream, hipEvent_t* marks = nullptr);
+hipError_t launch_window(const StepArgs& a, hipStream_t stream, hipEvent_t* marks = nullptr);
+
+// *base += add (one thread): advances the step base at the end of a replayed
+// sequence of windows.
+hipError_t launch_advance_base(int32_t* base, int32_t add, hipStream_t stream);
+// *base = value (one thread).
+hipError_t launch_set_base(int32_t* base, int32_t value, hipStream_t stream);
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s);

@@ -47,6 +47,20 @@ SIGNATURES = {
     "rdx_selftest_binom": ([C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_double, C.c_int64,
                             _p], C.c_int),
     "rdx_selftest_copy": ([C.c_int64, C.c_int32, C.POINTER(C.c_double)], C.c_int),
+    "rdx_set_exec_options": ([_p, _p], C.c_int),
+    "rdx_get_exec_options": ([_p, _p], C.c_int),
+    "rdx_batch_create": ([C.c_int32, _p, _p, _p, _p, C.POINTER(C.c_void_p)], C.c_int),
+    "rdx_batch_destroy": ([_p], None),
+    "rdx_batch_size": ([_p, C.POINTER(C.c_int32)], C.c_int),
+    "rdx_batch_get_run_info": ([_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
+    "rdx_batch_set_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
+    "rdx_batch_get_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
+    "rdx_batch_run": ([_p, _p, _p], C.c_int),
+    "rdx_batch_step": ([_p, C.c_int64, _p], C.c_int),
+    "rdx_batch_sync": ([_p, _p], C.c_int),
+    "rdx_batch_get_stats": ([_p, C.c_int32, _p, _p], C.c_int),
+    "rdx_batch_set_exec_options": ([_p, _p], C.c_int),
+    "rdx_batch_get_exec_options": ([_p, _p], C.c_int),
 }
 
 
@@ -100,6 +114,10 @@ class _Model(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_int64), ("voxel_steps", C.c_int64), ("ssa_events", C.c_int64),
                 ("moves", C.c_int64), ("t", C.c_double), ("window_index", C.c_int64)]
+
+
+class _ExecOptions(C.Structure):
+    _fields_ = [("autotune", C.c_int32), ("fast_grid_div", C.c_int32), ("graph_windows", C.c_int32)]
 
 
 class _KernelTimes(C.Structure):
@@ -236,6 +254,15 @@ class Sim:
     def set_kernel_timing(self, enable: bool):
         _check(lib().rdx_set_kernel_timing(self._h, int(bool(enable))), "rdx_set_kernel_timing")
 
+    def set_exec_options(self, autotune: bool = False, fast_grid_div: int = 1, graph_windows: int = 1):
+        o = _ExecOptions(int(bool(autotune)), int(fast_grid_div), int(graph_windows))
+        _check(lib().rdx_set_exec_options(self._h, C.byref(o)), "rdx_set_exec_options")
+
+    def exec_options(self) -> dict:
+        o = _ExecOptions()
+        _check(lib().rdx_get_exec_options(self._h, C.byref(o)), "rdx_get_exec_options")
+        return dict(autotune=o.autotune, fast_grid_div=o.fast_grid_div, graph_windows=o.graph_windows)
+
     def kernel_times(self, reset: bool = False) -> dict:
         kt = _KernelTimes()
         _check(lib().rdx_get_kernel_times(self._h, C.byref(kt), int(bool(reset))), "rdx_get_kernel_times")
@@ -259,6 +286,99 @@ class Sim:
     def load(self, blob: bytes, stream=None):
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib().rdx_load(self._h, buf, len(blob), _stream_ptr(stream)), "rdx_load")
+
+
+class Batch:
+    """Many independent runs advanced by the same window launches.
+
+    runs: sequence of (mesh, model, seed) or (mesh, model, seed, tau_override);
+    every model shares the species/reaction structure of the first.
+    """
+
+    def __init__(self, runs):
+        L = lib()
+        runs = list(runs)
+        n = len(runs)
+        meshes = (_Mesh * n)()
+        models = (_Model * n)()
+        seeds = (C.c_uint64 * n)()
+        taus = (C.c_double * n)()
+        self._keep = []
+        self.T, self.S, self.R = [], None, None
+        for i, r in enumerate(runs):
+            mesh, model, seed = r[0], r[1], r[2]
+            m, md, keep, T, S, R = _marshal(mesh, model)
+            meshes[i], models[i] = m, md
+            seeds[i] = int(seed) & (2**64 - 1)
+            taus[i] = float(r[3]) if len(r) > 3 else 0.0
+            self._keep.append(keep)
+            self.T.append(T)
+            self.S, self.R = S, R
+        h = C.c_void_p()
+        _check(L.rdx_batch_create(n, meshes, models, seeds, taus, C.byref(h)), "rdx_batch_create")
+        self._h = h
+        self._keep = None  # the library copied the inputs
+        self.n = n
+        self.tau = []
+        for i in range(n):
+            tau = C.c_double()
+            _check(L.rdx_batch_get_run_info(h, i, None, C.byref(tau)), "rdx_batch_get_run_info")
+            self.tau.append(tau.value)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rdx_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_counts(self, i: int, counts, stream=None):
+        if _is_torch_cuda(counts):
+            assert counts.dtype.itemsize == 4 and counts.is_contiguous() and counts.numel() == self.S * self.T[i]
+            _check(lib().rdx_batch_set_counts(self._h, i, counts.data_ptr(), 1, _stream_ptr(stream)),
+                   "rdx_batch_set_counts")
+        else:
+            c = np.ascontiguousarray(counts, np.int32).reshape(self.S, self.T[i])
+            _check(lib().rdx_batch_set_counts(self._h, i, _np_ptr(c), 0, _stream_ptr(stream)),
+                   "rdx_batch_set_counts")
+
+    def get_counts(self, i: int, out=None, stream=None):
+        if out is not None and _is_torch_cuda(out):
+            _check(lib().rdx_batch_get_counts(self._h, i, out.data_ptr(), 1, _stream_ptr(stream)),
+                   "rdx_batch_get_counts")
+            return out
+        c = np.zeros((self.S, self.T[i]), np.int32)
+        _check(lib().rdx_batch_get_counts(self._h, i, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_batch_get_counts")
+        return c
+
+    def run(self, t_end, stream=None):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t_end, np.float64), (self.n,)))
+        _check(lib().rdx_batch_run(self._h, _np_ptr(t), _stream_ptr(stream)), "rdx_batch_run")
+
+    def step(self, n_windows: int, stream=None):
+        _check(lib().rdx_batch_step(self._h, int(n_windows), _stream_ptr(stream)), "rdx_batch_step")
+
+    def sync(self, stream=None):
+        _check(lib().rdx_batch_sync(self._h, _stream_ptr(stream)), "rdx_batch_sync")
+
+    def stats(self, i: int, stream=None) -> Stats:
+        st = _Stats()
+        _check(lib().rdx_batch_get_stats(self._h, i, C.byref(st), _stream_ptr(stream)), "rdx_batch_get_stats")
+        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index)
+
+    def set_exec_options(self, autotune: bool = False, fast_grid_div: int = 1, graph_windows: int = 1):
+        o = _ExecOptions(int(bool(autotune)), int(fast_grid_div), int(graph_windows))
+        _check(lib().rdx_batch_set_exec_options(self._h, C.byref(o)), "rdx_batch_set_exec_options")
+
+    def exec_options(self) -> dict:
+        o = _ExecOptions()
+        _check(lib().rdx_batch_get_exec_options(self._h, C.byref(o)), "rdx_batch_get_exec_options")
+        return dict(autotune=o.autotune, fast_grid_div=o.fast_grid_div, graph_windows=o.graph_windows)
 
 
 # -- device self-tests of the random layer ------------------------------------
