@@ -231,6 +231,84 @@ rdx_status rdx_batch_get_stats(rdx_batch* batch, int32_t i, rdx_stats* stats, vo
 rdx_status rdx_batch_set_exec_options(rdx_batch* batch, const rdx_exec_options* opts);
 rdx_status rdx_batch_get_exec_options(const rdx_batch* batch, rdx_exec_options* opts);
 
+/* ---- served form: a request loop with continuous batching ----
+ *
+ * A server owns a device-memory budget and one worker thread.  Each submitted
+ * request (mesh, model parameters, seed, initial counts, t_end) is validated
+ * and set up (section 2.1) on the submitting thread, then queued.  Between
+ * scheduling ticks the worker admits queued requests in arrival order while
+ * the budget has room for their device state, runs one tick -- up to
+ * tick_windows windows of every resident request, in the same launches -- and
+ * retires requests that reached t_end, releasing their memory for the next
+ * admissions.  A request's result is bit-identical to the same simulation run
+ * alone (rdx_create, rdx_set_counts, rdx_run(t_end)).  Latency is measured
+ * from submission to retirement.
+ *
+ * All requests share the species/reaction structure given at creation
+ * (n_species, n_reactions, lhs, rhs); meshes, diffusion coefficients, rate
+ * constants and regions may differ per request.  Functions may be called
+ * from any thread; rdx_server_destroy cancels what is still queued or
+ * running and must not race with other calls on the same server. */
+typedef struct rdx_server rdx_server;
+
+typedef enum {
+  RDX_REQ_QUEUED = 0,
+  RDX_REQ_RUNNING = 1,
+  RDX_REQ_DONE = 2,
+  RDX_REQ_FAILED = 3,
+  RDX_REQ_CANCELLED = 4
+} rdx_request_state;
+
+typedef struct rdx_server_options {
+  size_t hbm_budget_bytes;  /* device memory for the worklist and the requests' state (>= 1 MiB) */
+  int32_t max_runs;         /* requests resident at once (0 = 1024) */
+  int32_t tick_windows;     /* windows per scheduling tick (0 = 8) */
+  int32_t graph_windows;    /* windows per captured graph (0 = tick_windows, 1 = plain launches) */
+} rdx_server_options;
+
+typedef struct rdx_request_info {
+  int32_t state;            /* rdx_request_state */
+  int32_t status;           /* rdx_status of a finished request */
+  int32_t n_tets;
+  int32_t n_species;
+  double t_submit;          /* seconds since server creation */
+  double t_admit;
+  double t_done;
+  rdx_stats stats;          /* tallies of a finished request */
+} rdx_request_info;
+
+typedef struct rdx_server_stats {
+  int64_t submitted, completed, failed, cancelled, queued, running, ticks;
+  int64_t voxel_steps, ssa_events, moves;  /* summed over completed requests */
+  double busy_s;            /* worker time spent in ticks */
+  double uptime_s;
+  double latency_p50_s;     /* nearest-rank quantiles of completion - submission */
+  double latency_p99_s;
+  int64_t capacity_tets;    /* worklist capacity derived from the budget */
+} rdx_server_stats;
+
+/* Errors: RDX_EINVAL (bad structure or options), RDX_ENOMEM, RDX_EHIP. */
+rdx_status rdx_server_create(const rdx_model* structure, const rdx_server_options* opts,
+                             rdx_server** out);
+void rdx_server_destroy(rdx_server* server);
+/* counts0 [n_species*n_tets] host pointer, copied.  *ticket identifies the
+ * request.  Errors: as rdx_create; RDX_EINVAL if the structure differs;
+ * RDX_EBUDGET if the request can never fit the budget; RDX_ESTATE while
+ * shutting down. */
+rdx_status rdx_server_submit(rdx_server* server, const rdx_mesh* mesh, const rdx_model* model,
+                             uint64_t seed, const int32_t* counts0, double t_end,
+                             double tau_override, int64_t* ticket);
+rdx_status rdx_server_poll(rdx_server* server, int64_t ticket, rdx_request_info* info);
+/* Blocks until the request is done, failed or cancelled (timeout_s < 0: no
+ * limit; on timeout RDX_ESTATE and the request stays).  A done request's
+ * counts go to counts_out (host, may be NULL).  Returns the request's status
+ * and forgets the ticket. */
+rdx_status rdx_server_wait(rdx_server* server, int64_t ticket, double timeout_s, int32_t* counts_out,
+                           rdx_request_info* info);
+/* Queued requests are dropped at once, running ones at the next tick boundary. */
+rdx_status rdx_server_cancel(rdx_server* server, int64_t ticket);
+rdx_status rdx_server_get_stats(rdx_server* server, rdx_server_stats* stats);
+
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* rdx_last_error(void);
 

@@ -145,6 +145,7 @@ class Engine {
   int64_t resident_tets() const { return resident_tets_; }
   int resident_runs() const { return resident_runs_; }
   int64_t max_tets() const { return max_tets_; }
+  int max_runs() const { return max_runs_; }
   const DeviceArena& arena() const { return arena_; }
 
  private:

@@ -61,6 +61,14 @@ SIGNATURES = {
     "rdx_batch_get_stats": ([_p, C.c_int32, _p, _p], C.c_int),
     "rdx_batch_set_exec_options": ([_p, _p], C.c_int),
     "rdx_batch_get_exec_options": ([_p, _p], C.c_int),
+    "rdx_server_create": ([_p, _p, C.POINTER(C.c_void_p)], C.c_int),
+    "rdx_server_destroy": ([_p], None),
+    "rdx_server_submit": ([_p, _p, _p, C.c_uint64, _p, C.c_double, C.c_double, C.POINTER(C.c_int64)],
+                          C.c_int),
+    "rdx_server_poll": ([_p, C.c_int64, _p], C.c_int),
+    "rdx_server_wait": ([_p, C.c_int64, C.c_double, _p, _p], C.c_int),
+    "rdx_server_cancel": ([_p, C.c_int64], C.c_int),
+    "rdx_server_get_stats": ([_p, _p], C.c_int),
 }
 
 
@@ -118,6 +126,27 @@ class _Stats(C.Structure):
 
 class _ExecOptions(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("fast_grid_div", C.c_int32), ("graph_windows", C.c_int32)]
+
+
+class _ServerOptions(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_runs", C.c_int32), ("tick_windows", C.c_int32),
+                ("graph_windows", C.c_int32)]
+
+
+class _RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("n_tets", C.c_int32), ("n_species", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("stats", _Stats)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "cancelled", "queued",
+                                         "running", "ticks", "voxel_steps", "ssa_events", "moves")] + \
+               [(n, C.c_double) for n in ("busy_s", "uptime_s", "latency_p50_s", "latency_p99_s")] + \
+               [("capacity_tets", C.c_int64)]
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
 class _KernelTimes(C.Structure):
@@ -379,6 +408,80 @@ class Batch:
         o = _ExecOptions()
         _check(lib().rdx_batch_get_exec_options(self._h, C.byref(o)), "rdx_batch_get_exec_options")
         return dict(autotune=o.autotune, fast_grid_div=o.fast_grid_div, graph_windows=o.graph_windows)
+
+
+def _info(ri: _RequestInfo) -> dict:
+    st = ri.stats
+    return dict(state=REQ_STATES.get(ri.state, ri.state), status=ri.status, n_tets=ri.n_tets,
+                t_submit=ri.t_submit, t_admit=ri.t_admit, t_done=ri.t_done,
+                latency_s=ri.t_done - ri.t_submit,
+                stats=Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index))
+
+
+class Server:
+    """Request loop with continuous batching over a device-memory budget.
+
+    structure: a model dict fixing the species/reaction structure shared by
+    every request."""
+
+    def __init__(self, structure: dict, hbm_budget_bytes: int, max_runs: int = 0, tick_windows: int = 0,
+                 graph_windows: int = 0):
+        L = lib()
+        m, md, keep, T, S, R = _marshal(_ONE_TET, structure)
+        o = _ServerOptions(int(hbm_budget_bytes), int(max_runs), int(tick_windows), int(graph_windows))
+        h = C.c_void_p()
+        _check(L.rdx_server_create(C.byref(md), C.byref(o), C.byref(h)), "rdx_server_create")
+        self._h = h
+        self.S = S
+        self._sizes = {}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rdx_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, mesh: dict, model: dict, seed: int, counts, t_end: float, tau_override: float = 0.0) -> int:
+        m, md, keep, T, S, R = _marshal(mesh, model)
+        c = np.ascontiguousarray(counts, np.int32).reshape(S, T)
+        tk = C.c_int64()
+        _check(lib().rdx_server_submit(self._h, C.byref(m), C.byref(md), int(seed) & (2**64 - 1), _np_ptr(c),
+                                       float(t_end), float(tau_override), C.byref(tk)), "rdx_server_submit")
+        self._sizes[tk.value] = (S, T)
+        return tk.value
+
+    def poll(self, ticket: int) -> dict:
+        ri = _RequestInfo()
+        _check(lib().rdx_server_poll(self._h, int(ticket), C.byref(ri)), "rdx_server_poll")
+        return _info(ri)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        """(counts [S, T], info); raises RdxError for failed or cancelled requests."""
+        S, T = self._sizes[ticket]
+        out = np.zeros((S, T), np.int32)
+        ri = _RequestInfo()
+        _check(lib().rdx_server_wait(self._h, int(ticket), float(timeout_s), _np_ptr(out), C.byref(ri)),
+               "rdx_server_wait")
+        self._sizes.pop(ticket, None)
+        return out, _info(ri)
+
+    def cancel(self, ticket: int):
+        _check(lib().rdx_server_cancel(self._h, int(ticket)), "rdx_server_cancel")
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().rdx_server_get_stats(self._h, C.byref(st)), "rdx_server_get_stats")
+        return {n: getattr(st, n) for n, _ in _ServerStats._fields_}
+
+
+_ONE_TET = dict(verts=np.array([[0, 0, 0], [1e-6, 0, 0], [0, 1e-6, 0], [0, 0, 1e-6]], np.float64),
+                tets=np.array([[0, 1, 2, 3]], np.int32))
 
 
 # -- device self-tests of the random layer ------------------------------------
