@@ -172,34 +172,66 @@ rdx_status build_instance(const rdx_mesh* mesh, const rdx_model* model, double t
     }
   }
 
-  // adjacency: sort all faces by their vertex triple; equal neighbours pair up
-  std::vector<FaceRecord> faces(4 * (size_t)T);
-  for (int32_t i = 0; i < T; ++i)
-    for (int k = 0; k < 4; ++k) {
-      FaceRecord& f = faces[4 * (size_t)i + k];
-      for (int j = 0; j < 3; ++j) f.key[j] = tets[4 * (size_t)i + kFace[k][j]];
-      std::sort(f.key.begin(), f.key.end());
-      f.tet = i;
-      f.face = k;
-    }
-  std::sort(faces.begin(), faces.end(), [](const FaceRecord& x, const FaceRecord& y) {
-    if (x.key != y.key) return x.key < y.key;
-    if (x.tet != y.tet) return x.tet < y.tet;
-    return x.face < y.face;
-  });
+  // adjacency: sort all faces by their vertex triple; equal neighbours pair
+  // up.  With fewer than 2^21 vertices the sorted triple packs into one
+  // 63-bit key and the records are 16 bytes; otherwise 20-byte records with
+  // a three-word key.  Both give the same pairs.
   I.nbr.assign(4 * (size_t)T, -1);
-  for (size_t a = 0; a < faces.size();) {
-    size_t b = a + 1;
-    while (b < faces.size() && faces[b].key == faces[a].key) ++b;
-    if (b - a > 2 || (b - a == 2 && faces[a].tet == faces[a + 1].tet)) {
-      *err = "a face is shared by more than two tets";
-      return RDX_EMESH;
+  auto pair_up = [&](size_t n, auto same_key, auto tf_of) -> bool {
+    for (size_t a = 0; a < n;) {
+      size_t b = a + 1;
+      while (b < n && same_key(a, b)) ++b;
+      if (b - a > 2 || (b - a == 2 && tf_of(a) / 4 == tf_of(a + 1) / 4)) return false;
+      if (b - a == 2) {
+        const int64_t x = tf_of(a), y = tf_of(a + 1);
+        I.nbr[(size_t)x] = (int32_t)(y / 4);
+        I.nbr[(size_t)y] = (int32_t)(x / 4);
+      }
+      a = b;
     }
-    if (b - a == 2) {
-      I.nbr[4 * (size_t)faces[a].tet + faces[a].face] = faces[a + 1].tet;
-      I.nbr[4 * (size_t)faces[a + 1].tet + faces[a + 1].face] = faces[a].tet;
-    }
-    a = b;
+    return true;
+  };
+  bool faces_ok;
+  if (mesh->n_verts <= (1 << 21)) {
+    struct Packed {
+      uint64_t key;
+      int64_t tf;  // 4 tet + face
+    };
+    std::vector<Packed> faces(4 * (size_t)T);
+    for (int32_t i = 0; i < T; ++i)
+      for (int k = 0; k < 4; ++k) {
+        int32_t v[3];
+        for (int j = 0; j < 3; ++j) v[j] = tets[4 * (size_t)i + kFace[k][j]];
+        std::sort(v, v + 3);
+        faces[4 * (size_t)i + k] = Packed{((uint64_t)v[0] << 42) | ((uint64_t)v[1] << 21) | (uint64_t)v[2],
+                                          4 * (int64_t)i + k};
+      }
+    std::sort(faces.begin(), faces.end(), [](const Packed& x, const Packed& y) {
+      return x.key != y.key ? x.key < y.key : x.tf < y.tf;
+    });
+    faces_ok = pair_up(faces.size(), [&](size_t a, size_t b) { return faces[a].key == faces[b].key; },
+                       [&](size_t a) { return faces[a].tf; });
+  } else {
+    std::vector<FaceRecord> faces(4 * (size_t)T);
+    for (int32_t i = 0; i < T; ++i)
+      for (int k = 0; k < 4; ++k) {
+        FaceRecord& f = faces[4 * (size_t)i + k];
+        for (int j = 0; j < 3; ++j) f.key[j] = tets[4 * (size_t)i + kFace[k][j]];
+        std::sort(f.key.begin(), f.key.end());
+        f.tet = i;
+        f.face = k;
+      }
+    std::sort(faces.begin(), faces.end(), [](const FaceRecord& x, const FaceRecord& y) {
+      if (x.key != y.key) return x.key < y.key;
+      if (x.tet != y.tet) return x.tet < y.tet;
+      return x.face < y.face;
+    });
+    faces_ok = pair_up(faces.size(), [&](size_t a, size_t b) { return faces[a].key == faces[b].key; },
+                       [&](size_t a) { return 4 * (int64_t)faces[a].tet + faces[a].face; });
+  }
+  if (!faces_ok) {
+    *err = "a face is shared by more than two tets";
+    return RDX_EMESH;
   }
 
   // couplings, their total, cumulative split fractions
