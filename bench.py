@@ -77,6 +77,135 @@ def cpu_baseline(workload, seconds: float = 12.0) -> dict:
             "ssa_events_per_s": inst.tallies.ssa_events / dt}
 
 
+def batched_leg(steps: int = 2) -> dict:
+    """1024 realisations of uneven size (6 x 6 x n slabs of 1 um cubes,
+    T ~ logU(1e3, 5e4)), A + B <-> C plus X -> Y -> Z with per-run rates
+    x U(0.5, 1.5), 1 s each: all runs in one batch (shared window launches,
+    launch shape tuned online, captured graphs) against the plain path (the
+    same runs one simulation at a time).  Both reset every run's counts from
+    device memory and run it to t_end inside the timed region; set-up is
+    outside it."""
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    runs = inputs.ensemble_runs()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    c0 = [torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev) for w in runs]
+    b = rdx.Batch([(w.mesh.as_dict(), w.model.as_dict(), w.seed) for w in runs])
+    t_end = [w.t_end for w in runs]
+
+    def batch_step():
+        for i in range(len(runs)):
+            b.set_counts(i, c0[i], stream=stream)
+        b.run(t_end, stream=stream)
+
+    batch_step()  # warm-up; also the online tuning of the launch shape
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch_step()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    vs = sum(b.stats(i).voxel_steps for i in range(len(runs)))
+    ev = sum(b.stats(i).ssa_events for i in range(len(runs)))
+    shape = b.exec_options()
+    b.close()
+
+    sims = [rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed) for w in runs]
+
+    def plain_step():
+        for s, c, w in zip(sims, c0, runs):
+            s.set_counts(c, stream=stream)
+            s.run(w.t_end, stream=stream)
+
+    plain_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_step()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / steps
+    vs_p = sum(s.stats().voxel_steps for s in sims)
+    for s in sims:
+        s.close()
+    return {"workload": "ensemble1024_box6x6xn_abc_chain", "runs": len(runs),
+            "total_tets": int(sum(w.mesh.n_tets for w in runs)),
+            "voxel_steps_per_step": vs, "ssa_events_per_step": ev,
+            "batched_voxel_steps_per_s": vs / tb, "batched_ssa_events_per_s": ev / tb,
+            "plain_voxel_steps_per_s": vs_p / tp, "speedup_vs_plain": tp / tb,
+            "batched_ms_per_step": tb * 1e3, "plain_ms_per_step": tp * 1e3,
+            "launch_shape": shape, "steps": steps}
+
+
+def serve_leg(n_requests: int = 400, rate: float = 200.0, submit_threads: int = 8) -> dict:
+    """Poisson arrivals (rate per s) of box-mesh requests, T ~ logU(1296, 2e5)
+    with the 10-species model, 100 ms each: the continuous-batching server
+    against the plain path serving the same stream first-in first-out, one
+    simulation at a time (create, set counts, run, read counts, destroy).
+    Latency = completion - scheduled arrival; each request's host set-up is
+    part of it in both."""
+    import concurrent.futures as cf
+    import numpy as np
+    from paper_1610_02258_amd import inputs, rdx
+
+    reqs = inputs.request_stream(n_requests=n_requests, rate_per_s=rate)
+    model = reqs[0][1].model.as_dict()
+    mesh_d = {}
+    for _, w in reqs:
+        mesh_d.setdefault(id(w.mesh), w.mesh.as_dict())
+
+    def pct(x, q):
+        return float(np.percentile(np.asarray(x), q, method="inverted_cdf"))
+
+    # continuous batching
+    srv = rdx.Server(model, hbm_budget_bytes=16 << 30, tick_windows=8)
+    t0 = time.perf_counter()
+    srv_t0 = t0
+
+    def submit(j):
+        arrival, w = reqs[j]
+        delay = t0 + arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        return srv.submit(mesh_d[id(w.mesh)], model, w.seed, w.counts, w.t_end)
+
+    with cf.ThreadPoolExecutor(submit_threads) as pool:
+        tickets = list(pool.map(submit, range(len(reqs))))
+    lat_s, vs = [], 0
+    for j, tk in enumerate(tickets):
+        _, info = srv.wait(tk)
+        lat_s.append(srv_t0 + info["t_done"] - (t0 + reqs[j][0]))
+        vs += info["stats"].voxel_steps
+    makespan_s = time.perf_counter() - t0
+    sst = srv.stats()
+    srv.close()
+
+    # plain FIFO
+    lat_p = []
+    t0 = time.perf_counter()
+    for arrival, w in reqs:
+        delay = t0 + arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        s = rdx.Sim(mesh_d[id(w.mesh)], model, w.seed)
+        s.set_counts(w.counts)
+        s.run(w.t_end)
+        s.get_counts()
+        s.close()
+        lat_p.append(time.perf_counter() - (t0 + arrival))
+    makespan_p = time.perf_counter() - t0
+    return {"workload": f"poisson{int(rate)}_box5x5xn_simple10", "requests": len(reqs),
+            "rate_per_s": rate, "mean_tets": float(np.mean([w.mesh.n_tets for _, w in reqs])),
+            "served_p50_s": pct(lat_s, 50), "served_p99_s": pct(lat_s, 99),
+            "plain_p50_s": pct(lat_p, 50), "plain_p99_s": pct(lat_p, 99),
+            "served_voxel_steps_per_s": vs / makespan_s, "plain_voxel_steps_per_s": vs / makespan_p,
+            "served_makespan_s": makespan_s, "plain_makespan_s": makespan_p,
+            "server_ticks": sst["ticks"], "server_busy_s": sst["busy_s"],
+            "submit_threads": submit_threads}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +213,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload is a single simulation on one "
@@ -168,10 +300,16 @@ def main() -> int:
                      "event_kernel_avg_us": avg_event_s * 1e6,
                      "window_us": elapsed * 1e6 / (windows_per_step * args.steps)},
     }
+    sim.close()
+    if not args.no_batched:
+        print("bench: batched ensemble leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg()
+    if not args.no_serve:
+        print("bench: serving leg", file=sys.stderr, flush=True)
+        out["served"] = serve_leg(args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    sim.close()
     return 0
 
 

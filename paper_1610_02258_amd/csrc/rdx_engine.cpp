@@ -199,7 +199,6 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipEventCreateWithFlags(&staged_, hipEventDisableTiming));
   RDX_HIP(hipEventCreate(&tune_ev_[0]));
   RDX_HIP(hipEventCreate(&tune_ev_[1]));
-  RDX_HIP(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
   RDX_HIP(hipMemcpy(model_, &model_host_, sizeof model_host_, hipMemcpyHostToDevice));
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
@@ -441,6 +440,7 @@ rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t s
   auto it = graphs_.find(key);
   if (it == graphs_.end()) {
     if (graphs_.size() >= 16) free_graphs();
+    if (!capture_stream_) RDX_HIP(hipStreamCreateWithFlags(&capture_stream_, hipStreamNonBlocking));
     // W windows and the step-base advance, captured once on a private stream
     StepArgs a = a0;
     RDX_HIP(hipStreamBeginCapture(capture_stream_, hipStreamCaptureModeThreadLocal));

@@ -248,9 +248,13 @@ def dendrite_mesh(target_tets: int = 1_000_000, total_length: float = 500 * UM,
 
 def tet_volumes_for_sampling(mesh: Mesh) -> np.ndarray:
     """|det|/6 per tet, vectorised; used only to place molecules uniformly."""
-    v = mesh.verts[mesh.tets]
-    a, b, c = v[:, 1] - v[:, 0], v[:, 2] - v[:, 0], v[:, 3] - v[:, 0]
-    return np.abs(np.einsum("ij,ij->i", a, np.cross(b, c))) / 6.0
+    P, t = mesh.verts, mesh.tets
+    p0 = P[t[:, 0]]
+    a, b, c = P[t[:, 1]] - p0, P[t[:, 2]] - p0, P[t[:, 3]] - p0
+    cx = b[:, 1] * c[:, 2] - b[:, 2] * c[:, 1]
+    cy = b[:, 2] * c[:, 0] - b[:, 0] * c[:, 2]
+    cz = b[:, 0] * c[:, 1] - b[:, 1] * c[:, 0]
+    return np.abs(a[:, 0] * cx + a[:, 1] * cy + a[:, 2] * cz) / 6.0
 
 
 def place_uniform(mesh: Mesh, totals, seed: int) -> np.ndarray:
@@ -263,6 +267,27 @@ def place_uniform(mesh: Mesh, totals, seed: int) -> np.ndarray:
     for s, n in enumerate(totals):
         if n > 0:
             out[s] = rng.multinomial(int(n), p)
+    return out
+
+
+def place_by_choice(mesh: Mesh, totals, seed: int) -> np.ndarray:
+    """Same law as :func:`place_uniform` (each molecule independently in a tet
+    chosen with probability proportional to its volume), drawn molecule by
+    molecule: cheaper when there are fewer molecules than tets."""
+    rng = np.random.default_rng(seed)
+    cdf = getattr(mesh, "_volume_cdf", None)
+    if cdf is None:
+        cdf = np.cumsum(tet_volumes_for_sampling(mesh))
+        cdf /= cdf[-1]
+        mesh._volume_cdf = cdf
+    out = np.zeros((len(totals), mesh.n_tets), np.int32)
+    for s, n in enumerate(totals):
+        if n > 0:
+            # the molecules' order does not matter for the counts; sorted
+            # uniforms make the table lookups sequential
+            idx = np.searchsorted(cdf, np.sort(rng.random(int(n))), side="right")
+            np.minimum(idx, mesh.n_tets - 1, out=idx)
+            out[s] = np.bincount(idx, minlength=mesh.n_tets)
     return out
 
 
@@ -426,14 +451,15 @@ def ensemble_runs(n_runs: int = 1024, seed: int = 3, t_lo: float = 1e3, t_hi: fl
     constants scaled by U(0.5, 1.5); molecule totals proportional to T."""
     rng = np.random.default_rng(seed)
     runs = []
+    meshes = {}
     for i in range(n_runs):
         T_target = math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))
         nz = max(1, int(round(T_target / 216.0)))
-        mesh = box_mesh(6, 6, nz, 1.0 * UM)
+        mesh = meshes.get(nz) or meshes.setdefault(nz, box_mesh(6, 6, nz, 1.0 * UM))
         model = model_abc_chain(rng.uniform(0.5, 1.5, 4))
         per = mesh.n_tets / 1296.0
         totals = [int(2000 * per), int(2000 * per), 0, int(1000 * per), 0, 0]
-        counts = place_uniform(mesh, totals, seed * 100003 + i)
+        counts = place_by_choice(mesh, totals, seed * 100003 + i)
         runs.append(Workload(f"run{i}", mesh, model, counts, seed * 1000003 + i, t_end))
     return runs
 
@@ -446,12 +472,13 @@ def request_stream(n_requests: int = 2000, rate_per_s: float = 200.0, seed: int 
     model = model_simple10(1)
     t = 0.0
     out = []
+    meshes = {}
     for i in range(n_requests):
         t += rng.exponential(1.0 / rate_per_s)
         T_target = math.exp(rng.uniform(math.log(t_lo), math.log(t_hi)))
         n = max(1, int(round((T_target / 6.0 / 25.0) ** 1.0)))
-        mesh = box_mesh(5, 5, n, 0.5 * UM)
+        mesh = meshes.get(n) or meshes.setdefault(n, box_mesh(5, 5, n, 0.5 * UM))
         totals = [int(2.0 * mesh.n_tets / 10)] * 10
-        counts = place_uniform(mesh, totals, seed * 7919 + i)
+        counts = place_by_choice(mesh, totals, seed * 7919 + i)
         out.append((t, Workload(f"req{i}", mesh, model, counts, seed * 104729 + i, t_end)))
     return out
