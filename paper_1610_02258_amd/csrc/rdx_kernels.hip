@@ -228,7 +228,7 @@ __device__ __forceinline__ double mass_action(int info, double k, int n0, int n1
 }
 
 template <int SMAX>
-__device__ __forceinline__ double propensity(const DevModel* __restrict__ M, int r, double k,
+__device__ __forceinline__ double propensity(const __attribute__((address_space(4))) DevModel* M, int r, double k,
                                              const int (&N)[SMAX], double nav, double inv_nav) {
   const int info = M->info[r];
   const int n0 = select_count<SMAX>(N, (info >> 8) & 0xff);
@@ -314,6 +314,44 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // atomics into the next count buffer.
 constexpr int kWave = 64;
 
+// Tables the window kernels only read -- the run table, the tile map, the
+// reaction tables, the step base and tile count -- are read through the
+// constant address space: nothing writes them while a kernel runs, and a
+// uniform address can then be served by a scalar load, whose wait does not
+// hold up the vector loads in flight.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+
+// Element j of a read-only int4 / double2 array through the constant address
+// space (the HIP vector types cannot be copied out of it directly).
+typedef int int4_v __attribute__((ext_vector_type(4)));
+typedef double double2_v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int4 ld_int4(const int4* p, size_t j) {
+  const int4_v v = ((cptr<int4_v>)p)[j];
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ double2 ld_double2(const double2* p, size_t j) {
+  const double2_v v = ((cptr<double2_v>)p)[j];
+  return make_double2(v.x, v.y);
+}
+
+// Every block of the window kernels is a single wave: its lanes execute in
+// lockstep and its LDS operations complete in issue order, so handing LDS
+// data from lane to lane only needs the compiler to keep the accesses in
+// program order (a wavefront-scope fence), not a workgroup barrier, whose
+// fence would also wait for every global load and atomic in flight.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
   const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
@@ -398,7 +436,7 @@ __device__ __forceinline__ TileRange tile_range(int b, int G, int n_tiles) {
 
 // The run a tile belongs to and what this step is for that run.
 struct TileCtx {
-  const RunDesc* rd;
+  cptr<RunDesc> rd;
   int run;
   int base;        // first tet of the tile, run-local
   int T;
@@ -410,12 +448,13 @@ struct TileCtx {
 };
 
 __device__ __forceinline__ TileCtx tile_ctx(const StepArgs& A, int tile, int k) {
-  const int2 tm = A.tile_map[tile];
-  const RunDesc* rd = A.runs + tm.x;
+  const int run = as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile];
+  const int first = as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile + 1];
+  const cptr<RunDesc> rd = as_const(A.runs) + run;
   TileCtx c;
   c.rd = rd;
-  c.run = tm.x;
-  c.base = tm.y;
+  c.run = run;
+  c.base = first;
   c.T = rd->T;
   c.active = k < rd->n_steps;
   c.window = rd->window0 + (uint32_t)k;
@@ -446,17 +485,16 @@ __device__ __forceinline__ void load_tet(const TileCtx& c, int S, int i, TetData
   d.gb = make_double2(0.0, 0.0);
   d.reg = 0;
   if (active) {
-    d.nav = c.rd->nav[i];
-    d.nb = reinterpret_cast<const int4*>(c.rd->nbr)[i];
-    const double2* gp = reinterpret_cast<const double2*>(c.rd->geo) + 2 * (size_t)i;
-    d.ga = gp[0];
-    d.gb = gp[1];
-    if (c.rd->region) d.reg = c.rd->region[i];
+    d.nav = as_const(c.rd->nav)[i];
+    d.nb = ld_int4(reinterpret_cast<const int4*>(c.rd->nbr), (size_t)i);
+    d.ga = ld_double2(reinterpret_cast<const double2*>(c.rd->geo), 2 * (size_t)i);
+    d.gb = ld_double2(reinterpret_cast<const double2*>(c.rd->geo), 2 * (size_t)i + 1);
+    if (c.rd->region) d.reg = as_const(c.rd->region)[i];
   }
 }
 
 __device__ __forceinline__ int step_index(const StepArgs& A) {
-  return (A.step_base ? *A.step_base : 0) + A.k_rel;
+  return (A.step_base ? *as_const(A.step_base) : 0) + A.k_rel;
 }
 
 // Persistent: each block (one wave) walks its tiles of 64 tets, issuing the
@@ -474,7 +512,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
   const int k = step_index(A);
-  const int n_tiles = *A.n_tiles;
+  const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
   int kc_run = -1, tally_run = -1;
   unsigned long long n_moved = 0;
@@ -488,46 +526,57 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   nc = cc;
 
   for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
-    if (tile + tr.stride < tr.end) {
-      nc = tile_ctx(A, tile + tr.stride, k);
-      load_tet<SMAX>(nc, S, nc.base + lane, nxt);
-    }
-    if (cc.active) {
-      const RunDesc* rd = cc.rd;
-      const int T = cc.T;
-      const int i = cc.base + lane;
-      const bool active = i < T;
+    const bool has_next = tile + tr.stride < tr.end;
+    // a tile whose run has no window in this step only forwards the prefetch
+    const bool run_active = cc.active;
+    const cptr<RunDesc> rd = cc.rd;
+    const int T = cc.T;
+    const int i = cc.base + lane;
+    const bool active = i < T;
+    const bool regions = rd->region != nullptr;
+    int errbits = 0;
+    double nav = 1.0;
+    int reg = 0;
+    if (run_active) {
       if (cc.run != tally_run) {  // tallies are kept per run
         const unsigned long long mv = wave_sum(n_moved);
-        if (lane == 0 && tally_run >= 0 && mv) atomicAdd(A.runs[tally_run].tally + 1, mv);
+        if (lane == 0 && tally_run >= 0 && mv) atomicAdd(as_const(A.runs)[tally_run].tally + 1, mv);
         tally_run = cc.run;
         n_moved = 0;
       }
-      const bool regions = rd->region != nullptr;
       if (regions && kc_run != cc.run) {
         for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
-          s_kc[x / RMAX][x % RMAX] = rd->kcst[(x / RMAX) * 32 + (x % RMAX)];
+          s_kc[x / RMAX][x % RMAX] = as_const(rd->kcst)[(x / RMAX) * 32 + (x % RMAX)];
         kc_run = cc.run;
       }
       if (lane == 0) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? cc.tau_k * rd->D[s] : 0.0;
       }
-      int errbits = 0;
+    }
+    // the tile's data moves from registers to LDS (or stays in a few
+    // registers) before the next tile's loads are issued, so that waiting for
+    // this tile's loads never waits for the next tile's (an inactive tile's
+    // data is all zero)
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) {
-        s_acc[s][lane] = cur.N[s];
-        if (cur.N[s] != 0) cc.cin[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
-        if (cur.N[s] > kCountCap) errbits |= kErrOverflow;
-      }
-      __syncthreads();
+    for (int s = 0; s < SMAX; ++s) s_acc[s][lane] = cur.N[s];
+    s_nbr[lane] = cur.nb;
+    s_geo[0][lane] = cur.ga;
+    s_geo[1][lane] = cur.gb;
+    nav = cur.nav;
+    reg = cur.reg;
+    wave_sync();
+    __builtin_amdgcn_sched_barrier(0);
+    if (has_next) {
+      nc = tile_ctx(A, tile + tr.stride, k);
+      load_tet<SMAX>(nc, S, nc.base + lane, nxt);
+    }
+    if (run_active) {
 
       // propensities a_r = c_r h_r(N), summed in reaction order; the reaction
       // table is uniform (scalar loads).  Two copies of the loop on the uniform
       // region flag keep each rate-constant load in one address space.
-      const double nav = cur.nav;
       const double inv_nav = 1.0 / nav;
-      const int reg = cur.reg;
       auto sum_propensities = [&](auto with_regions) {
         double acc = 0.0;
 #pragma unroll
@@ -536,7 +585,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
             const int info = A.info[r];
             double kr;
             if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
-            else kr = rd->kcst[r];
+            else kr = as_const(rd->kcst)[r];
             const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
             const int n0 = s0 < SMAX ? s_acc[s0][lane] : 0;
             const int n1 = s1 < SMAX ? s_acc[s1][lane] : 0;
@@ -569,42 +618,42 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
           A.wl_run[slot] = cc.run;
           A.wl_tet[slot] = i;
           A.wl_nav[slot] = nav;
-          reinterpret_cast<int4*>(A.wl_nbr)[slot] = cur.nb;
-          reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = cur.ga;
-          reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = cur.gb;
+          reinterpret_cast<int4*>(A.wl_nbr)[slot] = s_nbr[lane];
+          reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = s_geo[0][lane];
+          reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = s_geo[1][lane];
 #pragma unroll
           for (int s = 0; s < SMAX; ++s)
-            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = cur.N[s];
+            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = s_acc[s][lane];
         }
       }
 
       // no event: Nbar = N; items for the diffusion operator.  The accumulator
       // starts with what cannot leave (the event kernel handles listed tets).
       uint32_t mask = 0;
-      s_nbr[lane] = cur.nb;
-      s_geo[0][lane] = cur.ga;
-      s_geo[1][lane] = cur.gb;
+      const double Gl = s_geo[0][lane].x;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) {
-        int start = 0;
-        if (active && !event && s < S) {
-          if (rd->D[s] > 0.0 && cur.ga.x > 0.0 && cur.N[s] > 0) mask |= 1u << s;
-          else start = cur.N[s];
-        }
-        s_acc[s][lane] = start;
+        const int n = s_acc[s][lane];
+        if (active && !event && s < S && rd->D[s] > 0.0 && Gl > 0.0 && n > 0) mask |= 1u << s;
       }
       const int cnt = __popc(mask);
       const int incl = wave_inclusive_scan(cnt);
       const int total = __shfl(incl, kWave - 1);
       int pos = incl - cnt;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s)
+      for (int s = 0; s < SMAX; ++s) {
+        const int n = s_acc[s][lane];
+        if (n != 0) cc.cin[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
+        if (n > kCountCap) errbits |= kErrOverflow;
         if ((mask >> s) & 1u) {
           s_item[pos] = (uint16_t)((lane << 4) | s);
-          s_m[pos] = cur.N[s];
+          s_m[pos] = n;
           ++pos;
         }
-      __syncthreads();
+        // the accumulator starts with what cannot leave
+        s_acc[s][lane] = ((mask >> s) & 1u) || event || !active ? 0 : n;
+      }
+      wave_sync();
 
       const int base = cc.base;
       for (int j = lane; j < total; j += kWave) {
@@ -631,7 +680,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 #undef RDX_DEPOSIT
         n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
       }
-      __syncthreads();
+      wave_sync();
       // coalesced flush of the tile's own tets (other tiles add into them too)
       if (active) {
 #pragma unroll
@@ -641,14 +690,14 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
         }
       }
       if (errbits) atomicOr(rd->err, errbits);
-      __syncthreads();  // LDS is rebuilt for the next tile
+      wave_sync();  // LDS is rebuilt for the next tile
     }
     cc = nc;
     cur = nxt;
   }
 
   const unsigned long long mv = wave_sum(n_moved);
-  if (lane == 0 && tally_run >= 0 && mv) atomicAdd(A.runs[tally_run].tally + 1, mv);
+  if (lane == 0 && tally_run >= 0 && mv) atomicAdd(as_const(A.runs)[tally_run].tally + 1, mv);
 }
 
 // Adds v (per lane) to field f of each lane's run tally: one atomic per wave
@@ -660,9 +709,9 @@ __device__ __forceinline__ void add_run_tally(const StepArgs& A, int run, unsign
   const int r0 = __shfl(run, leader);
   if (__all(v == 0 || run == r0)) {
     const unsigned long long sum = wave_sum(v);
-    if ((int)(threadIdx.x & (kWave - 1)) == leader) atomicAdd(A.runs[r0].tally + f, sum);
+    if ((int)(threadIdx.x & (kWave - 1)) == leader) atomicAdd(as_const(A.runs)[r0].tally + f, sum);
   } else if (v) {
-    atomicAdd(A.runs[run].tally + f, v);
+    atomicAdd(as_const(A.runs)[run].tally + f, v);
   }
 }
 
@@ -688,7 +737,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
   if (blockIdx.x == 0 && lane == 0) A.wl_count[(k + 1) & 1] = 0;  // next window's list starts empty
   if ((int)blockIdx.x * kWave >= n_work) return;                   // whole block idle
 
-  const DevModel* __restrict__ M = A.model;
+  const cptr<DevModel> M = as_const(A.model);
   const int S = A.S, R = A.R;
   bool tables = false;
 
@@ -718,7 +767,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
       tables = true;
     }
-    const RunDesc* rd = A.runs + run;
+    const cptr<RunDesc> rd = as_const(A.runs) + run;
     uint32_t window = 0, key0 = 0, key1 = 0;
     double tau = 1.0;
     int32_t* cout = nullptr;
@@ -730,14 +779,14 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       key1 = rd->key1;
       cout = rd->cnt[(window + 1u) & 1u];
       T = rd->T;
-      const int reg = rd->region ? (int)rd->region[i] : 0;
+      const int reg = rd->region ? (int)as_const(rd->region)[i] : 0;
       for (int r = 0; r < RMAX; ++r)
-        if (r < R) s_k[r][lane] = rd->kcst[reg * 32 + r];
+        if (r < R) s_k[r][lane] = as_const(rd->kcst)[reg * 32 + r];
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) s_td[s][lane] = s < S ? tau * rd->D[s] : 0.0;
     }
     s_moved[lane] = 0;
-    __syncthreads();
+    wave_sync();
 
     unsigned long long n_ev = 0;
     int errbits = 0;
@@ -830,14 +879,14 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
 #pragma unroll
     for (int s = 0; s < SMAX; ++s)
       if ((mask >> s) & 1u) s_item[pos++] = (uint16_t)((lane << 4) | s);
-    __syncthreads();
+    wave_sync();
     for (int j = lane; j < total; j += kWave) {
       const int it = s_item[j];
       const int L = it >> 4, sp = it & 15;
       const int ti = s_tet[L];
       const int npost = s_npost[sp][L];
       const int4 tnb = s_nbr[L];
-      const RunDesc* trd = A.runs + s_run[L];
+      const cptr<RunDesc> trd = as_const(A.runs) + s_run[L];
       const uint32_t twin = s_win[L];
       const ItemMoves mv = sample_item(trd->key0, trd->key1, twin, ti, sp, s_nbar[sp][L], npost,
                                        tnb, s_geo[0][L], s_geo[1][L], s_td[sp][L]);
@@ -850,11 +899,11 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       const int moved = mv.o0 + mv.o1 + mv.o2 + mv.o3;
       if (moved) atomicAdd(&s_moved[L], (unsigned long long)moved);
     }
-    __syncthreads();
+    wave_sync();
     add_run_tally(A, run, active ? n_ev : 0ull, 0);
     add_run_tally(A, run, active ? s_moved[lane] : 0ull, 1);
     if (errbits) atomicOr(rd->err, errbits);
-    __syncthreads();  // the LDS item list is rebuilt for the next 64 entries
+    wave_sync();  // the LDS item list is rebuilt for the next 64 entries
   }
 }
 
