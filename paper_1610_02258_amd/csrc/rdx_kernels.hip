@@ -467,7 +467,9 @@ __device__ __forceinline__ TileCtx tile_ctx(const StepArgs& A, int tile, int k) 
 // Everything one lane reads from global memory for its tet.
 template <int SMAX>
 struct TetData {
-  int N[SMAX];
+  // counts as one vector value, so that a uniform (run-time) species index
+  // selects a register rather than spilling the array to memory
+  int __attribute__((ext_vector_type(SMAX))) N;
   double nav;
   int4 nb;
   double2 ga, gb;  // (G, cum0), (cum1, cum2)
@@ -497,25 +499,35 @@ __device__ __forceinline__ int step_index(const StepArgs& A) {
   return (A.step_base ? *as_const(A.step_base) : 0) + A.k_rel;
 }
 
-// Persistent: each block (one wave) walks its tiles of 64 tets, issuing the
-// loads of the next tile before working on the current one.
+// Persistent: each block (one wave) walks its tiles of 64 tets.  Per tile:
+// (1) the counts (in registers) give the propensities and a0; the tile's data
+// moves to LDS; (2) the next tile's loads are issued, so that they are in
+// flight during the rest; (3) the first SSA waiting time, the worklist, the
+// diffusion items and the flush.  Values that depend only on the run (rate
+// constants, tau_k D_s, the key) are fetched once per run change, not per
+// tile: a persistent block's tiles mostly belong to one run.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
-  __shared__ int s_acc[SMAX][kWave];         // counts (propensities), then next counts of own tets
-  __shared__ double s_tauD[SMAX];
-  __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
-  __shared__ int s_m[SMAX * kWave];          // count of the item's species
+  __shared__ int s_acc[SMAX][kWave];         // counts, then next counts of own tets
+  __shared__ double s_tauD[SMAX];            // tau_k D_s of the current run
+  __shared__ uint32_t s_item[SMAX * kWave];  // packed items: count << 10 | lane << 4 | species
   __shared__ int4 s_nbr[kWave];
   __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of a run with regions
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the current run by region
 
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
   const int k = step_index(A);
   const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
-  int kc_run = -1, tally_run = -1;
+  int cache_run = -1;
   unsigned long long n_moved = 0;
+  // per-run constants (uniform)
+  uint32_t key0 = 0, key1 = 0, dmask = 0;
+  bool regions = false;
+  double kc0[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) kc0[r] = 0.0;
 
   TileCtx cc, nc;
   TetData<SMAX> cur, nxt;
@@ -527,57 +539,42 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 
   for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
     const bool has_next = tile + tr.stride < tr.end;
-    // a tile whose run has no window in this step only forwards the prefetch
-    const bool run_active = cc.active;
+    const bool run_active = cc.active;  // else the tile only forwards the prefetch
     const cptr<RunDesc> rd = cc.rd;
     const int T = cc.T;
     const int i = cc.base + lane;
     const bool active = i < T;
-    const bool regions = rd->region != nullptr;
-    int errbits = 0;
-    double nav = 1.0;
-    int reg = 0;
-    if (run_active) {
-      if (cc.run != tally_run) {  // tallies are kept per run
+    if (run_active && cc.run != cache_run) {
+      if (cache_run >= 0) {  // tallies are kept per run
         const unsigned long long mv = wave_sum(n_moved);
-        if (lane == 0 && tally_run >= 0 && mv) atomicAdd(as_const(A.runs)[tally_run].tally + 1, mv);
-        tally_run = cc.run;
+        if (lane == 0 && mv) atomicAdd(as_const(A.runs)[cache_run].tally + 1, mv);
         n_moved = 0;
       }
-      if (regions && kc_run != cc.run) {
-        for (int x = lane; x < kMaxRegions * RMAX; x += kWave)
-          s_kc[x / RMAX][x % RMAX] = as_const(rd->kcst)[(x / RMAX) * 32 + (x % RMAX)];
-        kc_run = cc.run;
-      }
-      if (lane == 0) {
+      key0 = rd->key0;
+      key1 = rd->key1;
+      regions = rd->region != nullptr;
+      const cptr<double> kc = as_const(rd->kcst);
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) s_tauD[s] = s < S ? cc.tau_k * rd->D[s] : 0.0;
-      }
+      for (int r = 0; r < RMAX; ++r) kc0[r] = r < R ? kc[r] : 0.0;
+      if (regions)
+        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
+      const double d = lane < S ? rd->D[lane < SMAX ? lane : 0] : 0.0;
+      if (lane < SMAX) s_tauD[lane] = lane < S ? cc.tau_k * d : 0.0;
+      dmask = (uint32_t)__ballot(lane < S && d > 0.0);
+      cache_run = cc.run;
+      wave_sync();
     }
-    // the tile's data moves from registers to LDS (or stays in a few
-    // registers) before the next tile's loads are issued, so that waiting for
-    // this tile's loads never waits for the next tile's (an inactive tile's
-    // data is all zero)
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) s_acc[s][lane] = cur.N[s];
-    s_nbr[lane] = cur.nb;
-    s_geo[0][lane] = cur.ga;
-    s_geo[1][lane] = cur.gb;
-    nav = cur.nav;
-    reg = cur.reg;
-    wave_sync();
-    __builtin_amdgcn_sched_barrier(0);
-    if (has_next) {
-      nc = tile_ctx(A, tile + tr.stride, k);
-      load_tet<SMAX>(nc, S, nc.base + lane, nxt);
-    }
-    if (run_active) {
 
-      // propensities a_r = c_r h_r(N), summed in reaction order; the reaction
-      // table is uniform (scalar loads).  Two copies of the loop on the uniform
-      // region flag keep each rate-constant load in one address space.
+    // (1) propensities a_r = c_r h_r(N) from the counts in registers, summed
+    // in reaction order; reactant species are uniform register indices
+    const double nav = cur.nav;
+    const int reg = cur.reg;
+    double a0 = 0.0;
+    if (run_active) {
       const double inv_nav = 1.0 / nav;
-      auto sum_propensities = [&](auto with_regions) {
+      // two copies of the loop on the uniform region flag: rate constants
+      // from scalar registers, or per lane from LDS
+      auto sum = [&](auto with_regions) {
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
@@ -585,30 +582,49 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
             const int info = A.info[r];
             double kr;
             if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
-            else kr = as_const(rd->kcst)[r];
+            else kr = kc0[r];
             const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-            const int n0 = s0 < SMAX ? s_acc[s0][lane] : 0;
-            const int n1 = s1 < SMAX ? s_acc[s1][lane] : 0;
+            const int n0 = s0 < SMAX ? cur.N[s0] : 0;
+            const int n1 = s1 < SMAX ? cur.N[s1] : 0;
             acc = acc + mass_action(info, kr, n0, n1, nav, inv_nav);
           }
         }
         return acc;
       };
-      const double a0 = regions ? sum_propensities(std::true_type{}) : sum_propensities(std::false_type{});
+      a0 = regions ? sum(std::true_type{}) : sum(std::false_type{});
+    }
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) s_acc[s][lane] = cur.N[s];
+    s_nbr[lane] = cur.nb;
+    s_geo[0][lane] = cur.ga;
+    s_geo[1][lane] = cur.gb;
+    wave_sync();
+    // (2) the next tile's loads
+    __builtin_amdgcn_sched_barrier(0);
+    if (has_next) {
+      nc = tile_ctx(A, tile + tr.stride, k);
+      load_tet<SMAX>(nc, S, nc.base + lane, nxt);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 
-      // first waiting time: does an event fall inside the window?  Since
+    if (run_active) {
+      // (3) first waiting time: does an event fall inside the window?  Since
       // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
       // margin, far above the rounding of ln and of the division) certainly
       // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
       bool event = false;
       if (active && a0 > 0.0) {
-        Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
+        Draw53 st(key0, key1, 0u, (uint32_t)i, cc.window);
         const double u = st.oc();
         if (!(1.0 - u > (cc.tau_k * a0) * 1.0000001)) {
           const double t_reac = -ln_basic(u) / a0;
           event = !(0.0 + t_reac > cc.tau_k);
         }
       }
+      int n_own[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) n_own[s] = s_acc[s][lane];
+      const double Gl = s_geo[0][lane].x;
       const unsigned long long ballot = __ballot(event);
       if (ballot) {
         int slot = 0;
@@ -623,32 +639,29 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
           reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = s_geo[1][lane];
 #pragma unroll
           for (int s = 0; s < SMAX; ++s)
-            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = s_acc[s][lane];
+            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = n_own[s];
         }
       }
 
-      // no event: Nbar = N; items for the diffusion operator.  The accumulator
-      // starts with what cannot leave (the event kernel handles listed tets).
+      // no event: Nbar = N; items for the diffusion operator
       uint32_t mask = 0;
-      const double Gl = s_geo[0][lane].x;
+      if (active && !event && Gl > 0.0) {
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) {
-        const int n = s_acc[s][lane];
-        if (active && !event && s < S && rd->D[s] > 0.0 && Gl > 0.0 && n > 0) mask |= 1u << s;
+        for (int s = 0; s < SMAX; ++s)
+          if (((dmask >> s) & 1u) && n_own[s] > 0) mask |= 1u << s;
       }
       const int cnt = __popc(mask);
       const int incl = wave_inclusive_scan(cnt);
       const int total = __shfl(incl, kWave - 1);
       int pos = incl - cnt;
+      int errbits = 0;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) {
-        const int n = s_acc[s][lane];
-        if (n != 0) cc.cin[(size_t)s * T + i] = 0;  // the next window's (zeroed) target
+        const int n = n_own[s];
         if (n > kCountCap) errbits |= kErrOverflow;
         if ((mask >> s) & 1u) {
-          s_item[pos] = (uint16_t)((lane << 4) | s);
-          s_m[pos] = n;
-          ++pos;
+          // a count of 2^22 or more does not fit the packed field (0 marks it)
+          s_item[pos++] = ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
         }
         // the accumulator starts with what cannot leave
         s_acc[s][lane] = ((mask >> s) & 1u) || event || !active ? 0 : n;
@@ -657,12 +670,15 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 
       const int base = cc.base;
       for (int j = lane; j < total; j += kWave) {
-        const int it = s_item[j];
-        const int L = it >> 4, sp = it & 15;
-        const int m = s_m[j];
+        const uint32_t it = s_item[j];
+        const int L = (int)((it >> 4) & 63);
+        const int sp = (int)(it & 15);
+        int m = (int)(it >> 10);
+        if (m == 0) m = cc.cin[(size_t)sp * T + base + L];  // an unpacked large count
         const int4 tnb = s_nbr[L];
-        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, base + L, sp, (double)m, m,
-                                         tnb, s_geo[0][L], s_geo[1][L], s_tauD[sp]);
+        const double2 ga = s_geo[0][L], gb = s_geo[1][L];
+        const double tds = s_tauD[sp];
+        const ItemMoves mv = sample_item(key0, key1, cc.window, base + L, sp, (double)m, m, tnb, ga, gb, tds);
         // own remainder and moves to the tile's own tets go to LDS, the rest
         // to the next count buffer
         int32_t* __restrict__ out_s = cc.cout + (size_t)sp * T;
@@ -682,11 +698,16 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
       }
       wave_sync();
       // coalesced flush of the tile's own tets (other tiles add into them too)
+      int v[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) v[s] = s_acc[s][lane];
       if (active) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
-          const int v = s < S ? s_acc[s][lane] : 0;
-          if (v != 0) atomicAdd(cc.cout + (size_t)s * T + i, v);
+          if (s < S) {
+            if (v[s] != 0) atomicAdd(cc.cout + (size_t)s * T + i, v[s]);
+            cc.cin[(size_t)s * T + i] = 0;  // the target of the window after next
+          }
         }
       }
       if (errbits) atomicOr(rd->err, errbits);
@@ -697,7 +718,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   }
 
   const unsigned long long mv = wave_sum(n_moved);
-  if (lane == 0 && tally_run >= 0 && mv) atomicAdd(as_const(A.runs)[tally_run].tally + 1, mv);
+  if (lane == 0 && cache_run >= 0 && mv) atomicAdd(as_const(A.runs)[cache_run].tally + 1, mv);
 }
 
 // Adds v (per lane) to field f of each lane's run tally: one atomic per wave
