@@ -261,7 +261,7 @@ typedef enum {
 
 typedef struct rdx_server_options {
   size_t hbm_budget_bytes;  /* device memory for the worklist and the requests' state (>= 1 MiB) */
-  int32_t max_runs;         /* requests resident at once (0 = 1024) */
+  int32_t max_runs;         /* requests resident at once (0: up to 1024, as the budget allows) */
   int32_t tick_windows;     /* windows per scheduling tick (0 = 8) */
   int32_t graph_windows;    /* windows per captured graph (0 = tick_windows, 1 = plain launches) */
 } rdx_server_options;

@@ -345,7 +345,8 @@ rdx_status rdx_load(rdx_sim* s, const void* buf, size_t len, void* stream) {
   if (st == RDX_OK) st = s->eng.upload_counts(&r, counts, false, strm);
   if (st != RDX_OK) return st;
   unsigned long long tal[2] = {(unsigned long long)h.events, (unsigned long long)h.moves};
-  RDX_HIP(hipMemcpy(r.tally, tal, sizeof tal, hipMemcpyHostToDevice));
+  RDX_HIP(hipStreamSynchronize(strm));  // the tallies were cleared on this stream
+  RDX_HIP(hipMemcpy(r.tally, tal, sizeof tal, hipMemcpyHostToDevice));  // into slot 0
   r.t = h.t;
   r.windows_run = h.windows_run;
   r.voxel_steps = h.voxel_steps;

@@ -133,11 +133,12 @@ size_t Engine::run_bytes(const HostInstance& I) {
   const size_t T = (size_t)I.T, S = (size_t)I.S;
   size_t b = 2 * align_up(4 * S * T) + align_up(16 * T) + align_up(32 * T) + align_up(8 * T);
   if (I.n_regions > 1) b += align_up(T);
-  b += align_up(sizeof(double) * kMaxRegions * 32) + kGranule;  // rate constants; tallies + flag
+  b += align_up(sizeof(double) * kMaxRegions * 32);  // rate constants
+  b += align_up(sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t));  // tallies, error flag
   return b;
 }
 
-size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 4 + 4 * (size_t)S + 8 + 16 + 32; }
+size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 4 * (size_t)S + 8 + 16 + 32 + 1; }
 
 Engine::~Engine() {
   if (staged_) (void)hipEventSynchronize(staged_);
@@ -152,13 +153,12 @@ Engine::~Engine() {
   (void)hipFree(d_tile_map_);
   (void)hipFree(d_n_tiles_);
   (void)hipFree(d_base_);
-  (void)hipFree(wl_run_);
+  (void)hipFree(wl_tile_count_);
   (void)hipFree(wl_tet_);
   (void)hipFree(wl_cnt_);
   (void)hipFree(wl_nav_);
   (void)hipFree(wl_nbr_);
   (void)hipFree(wl_geo_);
-  (void)hipFree(wl_count_);
   if (h_runs_) (void)hipHostFree(h_runs_);
   if (h_tile_map_) (void)hipHostFree(h_tile_map_);
   if (h_n_tiles_) (void)hipHostFree(h_n_tiles_);
@@ -179,15 +179,18 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   max_tets_ = max_tets;
   max_tiles_ = (max_tets + 63) / 64 + max_runs;
   if (max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "too many tiles");
-  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>((max_tets + 63) / 64, 1024));
-  const size_t W = (size_t)max_tets;
+  // one block per tile up to 16384 tiles: a tile with listed tets then has a
+  // wave of its own (the SSA chains are latency-bound), and a block whose
+  // tiles have none ends at once
+  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>(max_tiles_, 16384));
+  if (64 * max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "worklist too large");
+  const size_t W = 64 * (size_t)max_tiles_;  // 64 worklist slots per tile
   bool ok = dev_alloc(&model_, 1) == hipSuccess && dev_alloc(&d_runs_, (size_t)max_runs) == hipSuccess &&
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
-            dev_alloc(&wl_run_, W) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess &&
+            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess &&
             dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
-            dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess &&
-            dev_alloc(&wl_count_, 2) == hipSuccess;
+            dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
@@ -202,7 +205,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemcpy(model_, &model_host_, sizeof model_host_, hipMemcpyHostToDevice));
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
-  RDX_HIP(hipMemset(wl_count_, 0, 2 * sizeof(int32_t)));
+  RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
   RDX_HIP(hipDeviceSynchronize());
   return RDX_OK;
 }
@@ -238,9 +241,10 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
   r->nav = reinterpret_cast<double*>(carve(8 * T));
   r->region = I.n_regions > 1 ? reinterpret_cast<uint8_t*>(carve(T)) : nullptr;
   r->kcst = reinterpret_cast<double*>(carve(sizeof(double) * kMaxRegions * 32));
-  char* misc = carve(kGranule);
+  const size_t misc_bytes = sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t);
+  char* misc = carve(misc_bytes);
   r->tally = reinterpret_cast<unsigned long long*>(misc);
-  r->err = reinterpret_cast<int32_t*>(misc + 2 * sizeof(unsigned long long));
+  r->err = reinterpret_cast<int32_t*>(misc + sizeof(unsigned long long) * 2 * kTallySlots);
 
   // host images of the interleaved couplings and the padded rate table; the
   // copies are synchronous so the images can go when this returns
@@ -261,7 +265,7 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
   if (e == hipSuccess) e = hipMemcpyAsync(r->kcst, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemsetAsync(r->cnt[0], 0, 4 * S * T, stream);
   if (e == hipSuccess) e = hipMemsetAsync(r->cnt[1], 0, 4 * S * T, stream);
-  if (e == hipSuccess) e = hipMemsetAsync(misc, 0, kGranule, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(misc, 0, misc_bytes, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     arena_.release(off);
@@ -289,7 +293,7 @@ void Engine::remove_run(Run* r, hipStream_t stream) {
 rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
   const size_t n = (size_t)r->host.S * (size_t)r->host.T;
   RDX_HIP(hipMemsetAsync(r->cnt[(r->window + 1) & 1], 0, sizeof(int32_t) * n, stream));
-  RDX_HIP(hipMemsetAsync(r->tally, 0, 2 * sizeof(unsigned long long), stream));
+  RDX_HIP(hipMemsetAsync(r->tally, 0, sizeof(unsigned long long) * 2 * kTallySlots, stream));
   RDX_HIP(hipMemsetAsync(r->err, 0, sizeof(int32_t), stream));
   return RDX_OK;
 }
@@ -505,16 +509,15 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.S = S_;
   a.R = R_;
   a.event_blocks = event_blocks_;
-  a.wl_stride = (int32_t)max_tets_;
+  a.wl_stride = (int32_t)(64 * max_tiles_);
   a.model = model_;
   std::memcpy(a.info, model_host_.info, sizeof a.info);
-  a.wl_run = wl_run_;
+  a.wl_tile_count = wl_tile_count_;
   a.wl_tet = wl_tet_;
   a.wl_cnt = wl_cnt_;
   a.wl_nav = wl_nav_;
   a.wl_nbr = wl_nbr_;
   a.wl_geo = wl_geo_;
-  a.wl_count = wl_count_;
 
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
     a.fast_grid = fast_grid_for(n_tiles, sh.fast_grid_div);
@@ -616,7 +619,13 @@ rdx_status Engine::run_error(const Run* r) const {
 }
 
 rdx_status Engine::run_tally(const Run* r, unsigned long long tal[2]) const {
-  RDX_HIP(hipMemcpy(tal, r->tally, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  unsigned long long slots[2 * kTallySlots];
+  RDX_HIP(hipMemcpy(slots, r->tally, sizeof slots, hipMemcpyDeviceToHost));
+  tal[0] = tal[1] = 0;
+  for (int j = 0; j < kTallySlots; ++j) {
+    tal[0] += slots[2 * j];
+    tal[1] += slots[2 * j + 1];
+  }
   return RDX_OK;
 }
 

@@ -63,7 +63,7 @@ struct Run {
   double* nav = nullptr;
   uint8_t* region = nullptr;  // only with more than one region
   double* kcst = nullptr;     // [8][32]
-  unsigned long long* tally = nullptr;
+  unsigned long long* tally = nullptr;  // [kTallySlots][2]
   int32_t* err = nullptr;
   double t = 0.0;
   int64_t window = 0;
@@ -95,7 +95,8 @@ class Engine {
 
   // Device bytes of one run's state (counts, mesh arrays, tables, tallies).
   static size_t run_bytes(const HostInstance& I);
-  // Worklist bytes per tet of capacity.
+  // Worklist bytes per tet of capacity (64 entries per tile, each tile
+  // of a run padded to 64 tets).
   static size_t worklist_bytes_per_tet(int S);
 
   // `proto` fixes the shared species/reaction structure.  arena_bytes holds
@@ -169,13 +170,12 @@ class Engine {
   int2* d_tile_map_ = nullptr;
   int32_t* d_n_tiles_ = nullptr;
   int32_t* d_base_ = nullptr;
-  int32_t* wl_run_ = nullptr;
+  int32_t* wl_tile_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
   int32_t* wl_cnt_ = nullptr;
   double* wl_nav_ = nullptr;
   int32_t* wl_nbr_ = nullptr;
   double* wl_geo_ = nullptr;
-  int32_t* wl_count_ = nullptr;
   int event_blocks_ = 1;
 
   // pinned staging of the run table and tile map; `staged_` marks the

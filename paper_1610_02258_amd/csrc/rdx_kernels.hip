@@ -98,16 +98,18 @@ struct Draw32 {
     ++call;
     pos = 0;
   }
+  // The stream's next Philox call (all four words unused).
+  __device__ __forceinline__ void refill() {
+    w0 = call;
+    w1 = sid;
+    w2 = tet;
+    w3 = win;
+    philox4x32_10(w0, w1, w2, w3, k0, k1);
+    ++call;
+    pos = 0;
+  }
   __device__ __forceinline__ double u() {
-    if (pos == 4) {
-      w0 = call;
-      w1 = sid;
-      w2 = tet;
-      w3 = win;
-      philox4x32_10(w0, w1, w2, w3, k0, k1);
-      ++call;
-      pos = 0;
-    }
+    if (pos == 4) refill();
     const uint32_t w = pos == 0 ? w0 : (pos == 1 ? w1 : (pos == 2 ? w2 : w3));
     ++pos;
     return (double)w * 0x1p-32;
@@ -402,16 +404,33 @@ __device__ __forceinline__ ItemMoves sample_item(uint32_t key0, uint32_t key1, u
   }
   const double t0 = scale * ga.y, t1 = scale * gb.x, t2 = scale * gb.y;
   int n = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-  for (long long j = 0; j < trials; ++j) {
-    const double u = sp.u();
-    if (u < scale && n < npost) {
-      const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
-      o0 += f == 0;
-      o1 += f == 1;
-      o2 += f == 2;
-      o3 += f == 3;
-      ++n;
+  // the draws in stream order, four words per Philox call: the words left in
+  // the current call, then whole calls; word q of a call is a register, so
+  // no draw needs a run-time select
+  long long j = 0;
+  int q0 = sp.pos;
+  while (j < trials) {
+    if (q0 == 4) {
+      sp.refill();
+      q0 = 0;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q >= q0 && j < trials) {
+        const uint32_t w = q == 0 ? sp.w0 : (q == 1 ? sp.w1 : (q == 2 ? sp.w2 : sp.w3));
+        const double u = (double)w * 0x1p-32;
+        if (u < scale && n < npost) {
+          const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
+          o0 += f == 0;
+          o1 += f == 1;
+          o2 += f == 2;
+          o3 += f == 3;
+          ++n;
+        }
+        ++j;
+      }
+    }
+    q0 = 4;
   }
   return ItemMoves{n, o0, o1, o2, o3};
 }
@@ -495,6 +514,10 @@ __device__ __forceinline__ void load_tet(const TileCtx& c, int S, int i, TetData
   }
 }
 
+__device__ __forceinline__ unsigned long long* tally_slot(const StepArgs& A, int run) {
+  return as_const(A.runs)[run].tally + 2 * (blockIdx.x & (kTallySlots - 1));
+}
+
 __device__ __forceinline__ int step_index(const StepArgs& A) {
   return (A.step_base ? *as_const(A.step_base) : 0) + A.k_rel;
 }
@@ -547,7 +570,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
     if (run_active && cc.run != cache_run) {
       if (cache_run >= 0) {  // tallies are kept per run
         const unsigned long long mv = wave_sum(n_moved);
-        if (lane == 0 && mv) atomicAdd(as_const(A.runs)[cache_run].tally + 1, mv);
+        if (lane == 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
         n_moved = 0;
       }
       key0 = rd->key0;
@@ -625,13 +648,12 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) n_own[s] = s_acc[s][lane];
       const double Gl = s_geo[0][lane].x;
+      // the tile's listed tets take its own worklist slots: no atomics
       const unsigned long long ballot = __ballot(event);
+      if (lane == 0) A.wl_tile_count[tile] = (int)__popcll(ballot);
       if (ballot) {
-        int slot = 0;
-        if (lane == 0) slot = atomicAdd(A.wl_count + (k & 1), (int)__popcll(ballot));
-        slot = __shfl(slot, 0) + (int)__popcll(ballot & ((1ull << lane) - 1ull));
+        const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
         if (event) {
-          A.wl_run[slot] = cc.run;
           A.wl_tet[slot] = i;
           A.wl_nav[slot] = nav;
           reinterpret_cast<int4*>(A.wl_nbr)[slot] = s_nbr[lane];
@@ -712,219 +734,205 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
       }
       if (errbits) atomicOr(rd->err, errbits);
       wave_sync();  // LDS is rebuilt for the next tile
+    } else if (lane == 0) {
+      A.wl_tile_count[tile] = 0;
     }
     cc = nc;
     cur = nxt;
   }
 
   const unsigned long long mv = wave_sum(n_moved);
-  if (lane == 0 && cache_run >= 0 && mv) atomicAdd(as_const(A.runs)[cache_run].tally + 1, mv);
+  if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
 }
 
-// Adds v (per lane) to field f of each lane's run tally: one atomic per wave
-// when all lanes with something to add belong to the same run.
-__device__ __forceinline__ void add_run_tally(const StepArgs& A, int run, unsigned long long v, int f) {
-  const unsigned long long has = __ballot(v != 0);
-  if (!has) return;
-  const int leader = __ffsll((long long)has) - 1;
-  const int r0 = __shfl(run, leader);
-  if (__all(v == 0 || run == r0)) {
-    const unsigned long long sum = wave_sum(v);
-    if ((int)(threadIdx.x & (kWave - 1)) == leader) atomicAdd(as_const(A.runs)[r0].tally + f, sum);
-  } else if (v) {
-    atomicAdd(as_const(A.runs)[run].tally + f, v);
-  }
-}
-
+// Event kernel: the full SSA window (composition-rejection, occupancy) and
+// the diffusion of the listed tets.  Block b scans the tiles b, b + G,
+// b + 2G, ... (one per lane) for listed entries, so the few tiles with
+// entries spread over the blocks; a tile's entries (one run) are processed
+// one per lane.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
   __shared__ int8_t s_delta[RMAX][SMAX];
   __shared__ unsigned long long s_deps[RMAX];
-  __shared__ double s_k[RMAX][kWave];        // rate constants of the lane's run and region
-  __shared__ double s_td[SMAX][kWave];       // tau_k D_s of the lane's run
-  __shared__ double s_nbar[SMAX][kWave];     // mean occupancy of item (lane, s)
-  __shared__ int s_npost[SMAX][kWave];       // post-reaction count of item (lane, s)
-  __shared__ uint16_t s_item[SMAX * kWave];  // packed items: lane << 4 | species
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the tile's run by region
+  __shared__ double s_td[SMAX];               // tau_k D_s of the tile's run
+  __shared__ double s_nbar[SMAX][kWave];      // mean occupancy of item (lane, s)
+  __shared__ int s_npost[SMAX][kWave];        // post-reaction count of item (lane, s)
+  __shared__ uint16_t s_item[SMAX * kWave];   // packed items: lane << 4 | species
   __shared__ int4 s_nbr[kWave];
-  __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
+  __shared__ double2 s_geo[2][kWave];         // (G, cum0), (cum1, cum2)
   __shared__ int s_tet[kWave];
-  __shared__ int s_run[kWave];
-  __shared__ uint32_t s_win[kWave];
-  __shared__ unsigned long long s_moved[kWave];
 
   const int lane = threadIdx.x;
   const int k = step_index(A);
-  const int n_work = A.wl_count[k & 1];
-  if (blockIdx.x == 0 && lane == 0) A.wl_count[(k + 1) & 1] = 0;  // next window's list starts empty
-  if ((int)blockIdx.x * kWave >= n_work) return;                   // whole block idle
-
+  const int n_tiles = *as_const(A.n_tiles);
+  const int G = gridDim.x;
   const cptr<DevModel> M = as_const(A.model);
   const int S = A.S, R = A.R;
   bool tables = false;
+  int cache_run = -1;
 
-  for (int e0 = blockIdx.x * kWave; e0 < n_work; e0 += gridDim.x * kWave) {
-    // the entry holds everything the tet needs: one round of loads
-    const int e = e0 + lane;
-    const bool active = e < n_work;
-    int run = 0, i = 0;
-    int N[SMAX];
-    double nav = 1.0;
-    int4 nb = make_int4(-1, -1, -1, -1);
-    double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
-    if (active) {
-      run = A.wl_run[e];
-      i = A.wl_tet[e];
-      nav = A.wl_nav[e];
-      nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
-      ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
-      gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
-    }
-    if (!tables) {  // reaction tables into LDS while the entry loads are in flight
-      for (int x = lane; x < RMAX * SMAX; x += kWave)
-        s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
-      for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
-      tables = true;
-    }
-    const cptr<RunDesc> rd = as_const(A.runs) + run;
-    uint32_t window = 0, key0 = 0, key1 = 0;
-    double tau = 1.0;
-    int32_t* cout = nullptr;
-    int T = 0;
-    if (active) {
-      window = rd->window0 + (uint32_t)k;
-      tau = k < rd->n_full ? rd->tau : rd->tau_last;
-      key0 = rd->key0;
-      key1 = rd->key1;
-      cout = rd->cnt[(window + 1u) & 1u];
-      T = rd->T;
-      const int reg = rd->region ? (int)as_const(rd->region)[i] : 0;
-      for (int r = 0; r < RMAX; ++r)
-        if (r < R) s_k[r][lane] = as_const(rd->kcst)[reg * 32 + r];
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) s_td[s][lane] = s < S ? tau * rd->D[s] : 0.0;
-    }
-    s_moved[lane] = 0;
-    wave_sync();
+  for (int t0 = blockIdx.x; t0 < n_tiles; t0 += kWave * G) {
+    const int tl = t0 + lane * G;
+    const int c = tl < n_tiles ? A.wl_tile_count[tl] : 0;
+    unsigned long long has = __ballot(c > 0);
+    while (has) {
+      const int b = __ffsll((long long)has) - 1;
+      has &= has - 1;
+      const int tile = t0 + b * G;
+      const int n_work = __shfl(c, b);
+      const TileCtx cc = tile_ctx(A, tile, k);
+      const cptr<RunDesc> rd = cc.rd;
+      const int T = cc.T;
+      const double tau = cc.tau_k;
 
-    unsigned long long n_ev = 0;
-    int errbits = 0;
-    uint32_t mask = 0;
-    if (active) {
-      const double inv_nav = 1.0 / nav;
-      double a[RMAX];
+      // the entry holds everything the tet needs: one round of loads
+      const bool active = lane < n_work;
+      const size_t e = (size_t)tile * kWave + lane;
+      int N[SMAX];
+      int i = 0;
+      double nav = 1.0;
+      int4 nb = make_int4(-1, -1, -1, -1);
+      double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int r = 0; r < RMAX; ++r)
-        a[r] = r < R ? propensity<SMAX>(M, r, s_k[r][lane], N, nav, inv_nav) : 0.0;
-
-      // ---- reaction SSA operator over [0, tau_k] ----
-      double O[SMAX], tS[SMAX];
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) {
-        O[s] = 0.0;
-        tS[s] = 0.0;
+      for (int s = 0; s < SMAX; ++s)
+        N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
+      if (active) {
+        i = A.wl_tet[e];
+        nav = A.wl_nav[e];
+        nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
+        ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
+        gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
       }
-      uint32_t touched = 0;
-      Draw53 st(key0, key1, 0u, (uint32_t)i, window);
-      double dt = 0.0;
-      unsigned int ev_tet = 0;
-      for (;;) {
-        double a0 = 0.0;
+      if (!tables) {  // reaction tables into LDS while the entry loads are in flight
+        for (int x = lane; x < RMAX * SMAX; x += kWave)
+          s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
+        for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
+        tables = true;
+      }
+      if (cc.run != cache_run) {  // per-run constants
+        const cptr<double> kc = as_const(rd->kcst);
+        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
+        if (lane < SMAX) s_td[lane] = lane < S ? tau * rd->D[lane] : 0.0;
+        cache_run = cc.run;
+      }
+      const int reg = (active && rd->region) ? (int)as_const(rd->region)[i] : 0;
+      wave_sync();
+
+      unsigned long long n_ev = 0, n_mv = 0;
+      int errbits = 0;
+      uint32_t mask = 0;
+      if (active) {
+        const double inv_nav = 1.0 / nav;
+        double a[RMAX];
 #pragma unroll
         for (int r = 0; r < RMAX; ++r)
-          if (r < R) a0 = a0 + a[r];
-        if (!(a0 > 0.0)) break;
-        const double u = st.oc();
-        const double t_reac = -ln_basic(u) / a0;
-        if (dt + t_reac > tau) break;
-        const int rn = cr_select<RMAX>(a, R, a0, st);
-        dt = dt + t_reac;
+          a[r] = r < R ? propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav) : 0.0;
+
+        // ---- reaction SSA operator over [0, tau_k] ----
+        double O[SMAX], tS[SMAX];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
-          if (s < S) {
-            const int d = s_delta[rn][s];
-            if (d != 0) {
-              O[s] = O[s] + (double)N[s] * (dt - tS[s]);
-              tS[s] = dt;
-              touched |= 1u << s;
-              N[s] += d;
-              if (N[s] > kCountCap) errbits |= kErrOverflow;
+          O[s] = 0.0;
+          tS[s] = 0.0;
+        }
+        uint32_t touched = 0;
+        Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
+        double dt = 0.0;
+        unsigned int ev_tet = 0;
+        for (;;) {
+          double a0 = 0.0;
+#pragma unroll
+          for (int r = 0; r < RMAX; ++r)
+            if (r < R) a0 = a0 + a[r];
+          if (!(a0 > 0.0)) break;
+          const double u = st.oc();
+          const double t_reac = -ln_basic(u) / a0;
+          if (dt + t_reac > tau) break;
+          const int rn = cr_select<RMAX>(a, R, a0, st);
+          dt = dt + t_reac;
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) {
+            if (s < S) {
+              const int d = s_delta[rn][s];
+              if (d != 0) {
+                O[s] = O[s] + (double)N[s] * (dt - tS[s]);
+                tS[s] = dt;
+                touched |= 1u << s;
+                N[s] += d;
+                if (N[s] > kCountCap) errbits |= kErrOverflow;
+              }
             }
           }
-        }
-        const unsigned long long dep = s_deps[rn];
+          const unsigned long long dep = s_deps[rn];
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r)
-          if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_k[r][lane], N, nav, inv_nav);
-        ++ev_tet;
-        if (errbits) break;
-        if (ev_tet >= (unsigned int)kEventCap) {
-          errbits |= kErrEvents;
-          break;
+          for (int r = 0; r < RMAX; ++r)
+            if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
+          ++ev_tet;
+          if (errbits) break;
+          if (ev_tet >= (unsigned int)kEventCap) {
+            errbits |= kErrEvents;
+            break;
+          }
         }
-      }
-      n_ev = ev_tet;
+        n_ev = ev_tet;
 
-      // ---- mean occupancies; items for the diffusion operator ----
-      s_tet[lane] = i;
-      s_run[lane] = run;
-      s_win[lane] = window;
-      s_nbr[lane] = nb;
-      s_geo[0][lane] = ga;
-      s_geo[1][lane] = gb;
+        // ---- mean occupancies; items for the diffusion operator ----
+        s_tet[lane] = i;
+        s_nbr[lane] = nb;
+        s_geo[0][lane] = ga;
+        s_geo[1][lane] = gb;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) {
-        if (s >= S) continue;
-        double nbar;
-        if ((touched >> s) & 1u) {
-          O[s] = O[s] + (double)N[s] * (tau - tS[s]);
-          nbar = O[s] / tau;
-        } else {
-          nbar = (double)N[s];
-        }
-        if (s_td[s][lane] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
-          mask |= 1u << s;
-          s_nbar[s][lane] = nbar;
-          s_npost[s][lane] = N[s];
-        } else if (N[s] != 0) {
-          atomicAdd(cout + (size_t)s * T + i, N[s]);  // nothing can leave
+        for (int s = 0; s < SMAX; ++s) {
+          if (s >= S) continue;
+          double nbar;
+          if ((touched >> s) & 1u) {
+            O[s] = O[s] + (double)N[s] * (tau - tS[s]);
+            nbar = O[s] / tau;
+          } else {
+            nbar = (double)N[s];
+          }
+          if (s_td[s] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
+            mask |= 1u << s;
+            s_nbar[s][lane] = nbar;
+            s_npost[s][lane] = N[s];
+          } else if (N[s] != 0) {
+            atomicAdd(cc.cout + (size_t)s * T + i, N[s]);  // nothing can leave
+          }
         }
       }
-    }
-    const int cnt = __popc(mask);
-    const int incl = wave_inclusive_scan(cnt);
-    const int total = __shfl(incl, kWave - 1);
-    int pos = incl - cnt;
+      const int cnt = __popc(mask);
+      const int incl = wave_inclusive_scan(cnt);
+      const int total = __shfl(incl, kWave - 1);
+      int pos = incl - cnt;
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if ((mask >> s) & 1u) s_item[pos++] = (uint16_t)((lane << 4) | s);
-    wave_sync();
-    for (int j = lane; j < total; j += kWave) {
-      const int it = s_item[j];
-      const int L = it >> 4, sp = it & 15;
-      const int ti = s_tet[L];
-      const int npost = s_npost[sp][L];
-      const int4 tnb = s_nbr[L];
-      const cptr<RunDesc> trd = as_const(A.runs) + s_run[L];
-      const uint32_t twin = s_win[L];
-      const ItemMoves mv = sample_item(trd->key0, trd->key1, twin, ti, sp, s_nbar[sp][L], npost,
-                                       tnb, s_geo[0][L], s_geo[1][L], s_td[sp][L]);
-      int32_t* out_s = trd->cnt[(twin + 1u) & 1u] + (size_t)sp * trd->T;
-      if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
-      if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
-      if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
-      if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
-      if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
-      const int moved = mv.o0 + mv.o1 + mv.o2 + mv.o3;
-      if (moved) atomicAdd(&s_moved[L], (unsigned long long)moved);
+      for (int s = 0; s < SMAX; ++s)
+        if ((mask >> s) & 1u) s_item[pos++] = (uint16_t)((lane << 4) | s);
+      wave_sync();
+      for (int j = lane; j < total; j += kWave) {
+        const int it = s_item[j];
+        const int L = it >> 4, sp = it & 15;
+        const int ti = s_tet[L];
+        const int npost = s_npost[sp][L];
+        const int4 tnb = s_nbr[L];
+        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, s_nbar[sp][L], npost,
+                                         tnb, s_geo[0][L], s_geo[1][L], s_td[sp]);
+        int32_t* out_s = cc.cout + (size_t)sp * T;
+        if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
+        if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
+        if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
+        if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
+        if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
+        n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+      }
+      const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv);
+      if (lane == 0) {
+        if (ev_sum) atomicAdd(tally_slot(A, cc.run), ev_sum);
+        if (mv_sum) atomicAdd(tally_slot(A, cc.run) + 1, mv_sum);
+      }
+      if (errbits) atomicOr(rd->err, errbits);
+      wave_sync();  // LDS is rebuilt for the next tile
     }
-    wave_sync();
-    add_run_tally(A, run, active ? n_ev : 0ull, 0);
-    add_run_tally(A, run, active ? s_moved[lane] : 0ull, 1);
-    if (errbits) atomicOr(rd->err, errbits);
-    wave_sync();  // the LDS item list is rebuilt for the next 64 entries
   }
 }
 

@@ -33,7 +33,7 @@ struct alignas(16) RunDesc {
   const double* nav;           // [T] N_A V[L]
   const uint8_t* region;       // [T] region labels, nullptr when the model has one region
   const double* kcst;          // [8][32] rate constants by region
-  unsigned long long* tally;   // [2] SSA events, molecules moved
+  unsigned long long* tally;   // [kTallySlots][2] SSA events, molecules moved (summed on read)
   int32_t* err;                // error-flag bits
   int32_t T;
   int32_t n_steps;             // windows of the current sequence (steps 0 .. n_steps-1)
@@ -55,18 +55,23 @@ struct StepArgs {
   int32_t S, R;
   int32_t fast_grid;           // persistent grid of the all-tets kernel
   int32_t event_blocks;        // grid of the event kernel
-  int32_t wl_stride;           // worklist capacity (row stride of wl_cnt)
+  int32_t wl_stride;           // worklist capacity, 64 entries per tile (row stride of wl_cnt)
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
-  // worklist of the tets whose first SSA event falls inside the window
-  int32_t* wl_run;
+  // worklist of the tets whose first SSA event falls inside the window: the
+  // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
+  int32_t* wl_tile_count;      // [tiles]
   int32_t* wl_tet;
   int32_t* wl_cnt;             // [S][wl_stride]
   double* wl_nav;
   int32_t* wl_nbr;             // [wl_stride][4]
   double* wl_geo;              // [wl_stride][4]
-  int32_t* wl_count;           // [2] list lengths by step parity
 };
+
+// Tallies are spread over this many slots per run (block b adds to slot
+// b mod kTallySlots), so that blocks finishing together do not queue on one
+// address.
+constexpr int kTallySlots = 64;
 
 // Resident-grid size of the all-tets kernel for (S, R): occupancy x compute units.
 int fast_grid_resident(int S, int R);

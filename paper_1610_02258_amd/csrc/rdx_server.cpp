@@ -239,13 +239,22 @@ rdx_status rdx_server_create(const rdx_model* structure, const rdx_server_option
   std::unique_ptr<rdx_server> s(new (std::nothrow) rdx_server());
   if (!s) return set_error(RDX_ENOMEM, "host allocation failed");
   (void)hipGetDevice(&s->device);
-  const int max_runs = opts->max_runs ? opts->max_runs : 1024;
+  // default: at most 1024 resident requests, and their padded worklist tiles
+  // at most an eighth of the budget
+  const size_t wl_tet0 = Engine::worklist_bytes_per_tet(proto.S);
+  const int max_runs = opts->max_runs
+                           ? opts->max_runs
+                           : (int)std::max<size_t>(1, std::min<size_t>(1024, opts->hbm_budget_bytes / (512 * wl_tet0)));
   s->tick_windows = opts->tick_windows ? opts->tick_windows : 8;
-  // the budget holds the worklist (per tet of capacity) and the runs' state
-  const size_t per_tet = Engine::worklist_bytes_per_tet(proto.S) + 8 * (size_t)proto.S + 57;
-  int64_t cap = (int64_t)(opts->hbm_budget_bytes / per_tet);
-  cap = std::min<int64_t>(cap, INT32_MAX / 2);
-  const size_t wl = (size_t)cap * Engine::worklist_bytes_per_tet(proto.S);
+  // the budget holds the worklist (per tet of capacity, plus a padded tile
+  // per resident run) and the runs' state
+  const size_t wl_tet = Engine::worklist_bytes_per_tet(proto.S);
+  const size_t pad = 64 * (size_t)max_runs * wl_tet;
+  if (opts->hbm_budget_bytes < 2 * pad) return set_error(RDX_EINVAL, "budget too small for max_runs");
+  const size_t per_tet = wl_tet + 8 * (size_t)proto.S + 57;
+  int64_t cap = (int64_t)((opts->hbm_budget_bytes - pad) / per_tet);
+  cap = std::min<int64_t>(cap, INT32_MAX / 256);
+  const size_t wl = (size_t)cap * wl_tet + pad;
   const size_t arena = opts->hbm_budget_bytes - wl;
   s->capacity_tets = cap;
   st = s->eng.init(proto, arena, max_runs, cap);
