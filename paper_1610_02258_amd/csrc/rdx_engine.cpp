@@ -138,7 +138,7 @@ size_t Engine::run_bytes(const HostInstance& I) {
   return b;
 }
 
-size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 4 * (size_t)S + 8 + 16 + 32 + 1; }
+size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 1 + 4 * (size_t)S + 8 + 16 + 32 + 1; }
 
 Engine::~Engine() {
   if (staged_) (void)hipEventSynchronize(staged_);
@@ -155,6 +155,7 @@ Engine::~Engine() {
   (void)hipFree(d_base_);
   (void)hipFree(wl_tile_count_);
   (void)hipFree(wl_tet_);
+  (void)hipFree(wl_reg_);
   (void)hipFree(wl_cnt_);
   (void)hipFree(wl_nav_);
   (void)hipFree(wl_nbr_);
@@ -188,7 +189,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   bool ok = dev_alloc(&model_, 1) == hipSuccess && dev_alloc(&d_runs_, (size_t)max_runs) == hipSuccess &&
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
-            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess &&
+            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
             dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
             dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
@@ -514,6 +515,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   std::memcpy(a.info, model_host_.info, sizeof a.info);
   a.wl_tile_count = wl_tile_count_;
   a.wl_tet = wl_tet_;
+  a.wl_reg = wl_reg_;
   a.wl_cnt = wl_cnt_;
   a.wl_nav = wl_nav_;
   a.wl_nbr = wl_nbr_;

@@ -172,6 +172,7 @@ class Engine {
   int32_t* d_base_ = nullptr;
   int32_t* wl_tile_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
+  uint8_t* wl_reg_ = nullptr;
   int32_t* wl_cnt_ = nullptr;
   double* wl_nav_ = nullptr;
   int32_t* wl_nbr_ = nullptr;

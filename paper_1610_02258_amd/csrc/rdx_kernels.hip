@@ -656,6 +656,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
         if (event) {
           A.wl_tet[slot] = i;
           A.wl_nav[slot] = nav;
+          A.wl_reg[slot] = (uint8_t)reg;
           reinterpret_cast<int4*>(A.wl_nbr)[slot] = s_nbr[lane];
           reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = s_geo[0][lane];
           reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = s_geo[1][lane];
@@ -752,9 +753,11 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 // one per lane.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
-  __shared__ int8_t s_delta[RMAX][SMAX];
-  __shared__ unsigned long long s_deps[RMAX];
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the tile's run by region
+  // reaction tables (copied whole from the device model) and the rate
+  // constants of the tile's run by region, filled with one round of loads
+  __shared__ uint32_t s_delta_w[32 * 16 / 4];   // int8 [32][16]
+  __shared__ uint32_t s_deps_w[32 * 2];         // uint64 [32]
+  __shared__ uint32_t s_kc_w[kMaxRegions * 32 * 2];  // double [8][32]
   __shared__ double s_td[SMAX];               // tau_k D_s of the tile's run
   __shared__ double s_nbar[SMAX][kWave];      // mean occupancy of item (lane, s)
   __shared__ int s_npost[SMAX][kWave];        // post-reaction count of item (lane, s)
@@ -804,20 +807,42 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
         ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
         gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
       }
-      if (!tables) {  // reaction tables into LDS while the entry loads are in flight
-        for (int x = lane; x < RMAX * SMAX; x += kWave)
-          s_delta[x / SMAX][x % SMAX] = M->delta[x / SMAX][x % SMAX];
-        for (int x = lane; x < RMAX; x += kWave) s_deps[x] = M->deps[x];
+      // tables and per-run constants: every load issued before any is used
+      const bool need_tables = !tables, need_run = cc.run != cache_run;
+      const bool regions = rd->region != nullptr;
+      const cptr<uint32_t> mw = as_const(reinterpret_cast<const uint32_t*>(A.model));
+      const cptr<uint32_t> kw = as_const(reinterpret_cast<const uint32_t*>(rd->kcst));
+      uint32_t d0 = 0, d1 = 0, dp = 0, kv[kMaxRegions];
+      double dv = 0.0;
+      int reg = 0;
+      if (need_tables) {
+        d0 = mw[offsetof(DevModel, delta) / 4 + lane];
+        d1 = mw[offsetof(DevModel, delta) / 4 + kWave + lane];
+        dp = mw[offsetof(DevModel, deps) / 4 + lane];
+      }
+      if (need_run) {
+#pragma unroll
+        for (int q = 0; q < kMaxRegions; ++q) kv[q] = (q == 0 || regions) ? kw[q * kWave + lane] : 0u;
+        if (lane < SMAX && lane < S) dv = rd->D[lane];
+      }
+      if (active && regions) reg = A.wl_reg[e];
+      if (need_tables) {
+        s_delta_w[lane] = d0;
+        s_delta_w[kWave + lane] = d1;
+        s_deps_w[lane] = dp;
         tables = true;
       }
-      if (cc.run != cache_run) {  // per-run constants
-        const cptr<double> kc = as_const(rd->kcst);
-        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
-        if (lane < SMAX) s_td[lane] = lane < S ? tau * rd->D[lane] : 0.0;
+      if (need_run) {
+#pragma unroll
+        for (int q = 0; q < kMaxRegions; ++q)
+          if (q == 0 || regions) s_kc_w[q * kWave + lane] = kv[q];
+        if (lane < SMAX) s_td[lane] = lane < S ? tau * dv : 0.0;
         cache_run = cc.run;
       }
-      const int reg = (active && rd->region) ? (int)as_const(rd->region)[i] : 0;
       wave_sync();
+      const int8_t(*s_delta)[16] = reinterpret_cast<const int8_t(*)[16]>(s_delta_w);
+      const unsigned long long* s_deps = reinterpret_cast<const unsigned long long*>(s_deps_w);
+      const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(s_kc_w);
 
       unsigned long long n_ev = 0, n_mv = 0;
       int errbits = 0;

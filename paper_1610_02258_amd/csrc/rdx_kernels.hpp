@@ -62,6 +62,7 @@ struct StepArgs {
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
   int32_t* wl_tile_count;      // [tiles]
   int32_t* wl_tet;
+  uint8_t* wl_reg;             // region label
   int32_t* wl_cnt;             // [S][wl_stride]
   double* wl_nav;
   int32_t* wl_nbr;             // [wl_stride][4]
