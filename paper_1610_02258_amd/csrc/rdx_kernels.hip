@@ -355,13 +355,16 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
-  const int lane = threadIdx.x & (kWave - 1);
+  // v in [0, 31]: the sum over lanes <= this one, one bit plane at a time
+  // (five ballots and bit counts; no LDS traffic)
+  int acc = 0;
 #pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int u = __shfl_up(v, off);
-    if (lane >= off) v += u;
+  for (int b = 0; b < 5; ++b) {
+    const unsigned long long m = __ballot((v >> b) & 1);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    acc += (int)((below + (uint32_t)((v >> b) & 1)) << b);
   }
-  return v;
+  return acc;
 }
 
 // Leavers of one item and their faces.  m = nbar stochastically rounded (a
@@ -746,6 +749,32 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
 }
 
+// a_r = c_r h_r(N) for every reaction, h by the reaction's order from the
+// packed (uniform) reaction entry; values below 2^-1000 are taken as zero.
+template <int SMAX, int RMAX, typename NV>
+__device__ __forceinline__ void all_propensities(const StepArgs& A, int R, const double (&c)[RMAX], const NV& N,
+                                                 double (&a)[RMAX]) {
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    double v = 0.0;
+    if (r < R) {
+      const int info = A.info[r];
+      const int order = info & 0xff;
+      const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+      const int n0 = s0 < SMAX ? N[s0] : 0;
+      const int n1 = s1 < SMAX ? N[s1] : 0;
+      double h;
+      if (order == 0) h = 1.0;
+      else if (order == 1) h = (double)n0;
+      else if (s0 == s1) h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
+      else h = (double)n0 * (double)n1;
+      v = c[r] * h;
+      v = v >= 0x1p-1000 ? v : 0.0;
+    }
+    a[r] = v;
+  }
+}
+
 // Event kernel: the full SSA window (composition-rejection, occupancy) and
 // the diffusion of the listed tets.  Block b scans the tiles b, b + G,
 // b + 2G, ... (one per lane) for listed entries, so the few tiles with
@@ -753,10 +782,9 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 // one per lane.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
-  // reaction tables (copied whole from the device model) and the rate
+  // net changes (copied whole from the device model) and the rate
   // constants of the tile's run by region, filled with one round of loads
   __shared__ uint32_t s_delta_w[32 * 16 / 4];   // int8 [32][16]
-  __shared__ uint32_t s_deps_w[32 * 2];         // uint64 [32]
   __shared__ uint32_t s_kc_w[kMaxRegions * 32 * 2];  // double [8][32]
   __shared__ double s_td[SMAX];               // tau_k D_s of the tile's run
   __shared__ double s_nbar[SMAX][kWave];      // mean occupancy of item (lane, s)
@@ -770,10 +798,10 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
   const int k = step_index(A);
   const int n_tiles = *as_const(A.n_tiles);
   const int G = gridDim.x;
-  const cptr<DevModel> M = as_const(A.model);
   const int S = A.S, R = A.R;
   bool tables = false;
   int cache_run = -1;
+  uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
 
   for (int t0 = blockIdx.x; t0 < n_tiles; t0 += kWave * G) {
     const int tl = t0 + lane * G;
@@ -812,13 +840,12 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       const bool regions = rd->region != nullptr;
       const cptr<uint32_t> mw = as_const(reinterpret_cast<const uint32_t*>(A.model));
       const cptr<uint32_t> kw = as_const(reinterpret_cast<const uint32_t*>(rd->kcst));
-      uint32_t d0 = 0, d1 = 0, dp = 0, kv[kMaxRegions];
+      uint32_t d0 = 0, d1 = 0, kv[kMaxRegions];
       double dv = 0.0;
       int reg = 0;
       if (need_tables) {
         d0 = mw[offsetof(DevModel, delta) / 4 + lane];
         d1 = mw[offsetof(DevModel, delta) / 4 + kWave + lane];
-        dp = mw[offsetof(DevModel, deps) / 4 + lane];
       }
       if (need_run) {
 #pragma unroll
@@ -829,7 +856,6 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       if (need_tables) {
         s_delta_w[lane] = d0;
         s_delta_w[kWave + lane] = d1;
-        s_deps_w[lane] = dp;
         tables = true;
       }
       if (need_run) {
@@ -837,24 +863,35 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
         for (int q = 0; q < kMaxRegions; ++q)
           if (q == 0 || regions) s_kc_w[q * kWave + lane] = kv[q];
         if (lane < SMAX) s_td[lane] = lane < S ? tau * dv : 0.0;
+        dmask = (uint32_t)__ballot(lane < SMAX && lane < S && tau * dv > 0.0);
         cache_run = cc.run;
       }
       wave_sync();
-      const int8_t(*s_delta)[16] = reinterpret_cast<const int8_t(*)[16]>(s_delta_w);
-      const unsigned long long* s_deps = reinterpret_cast<const unsigned long long*>(s_deps_w);
       const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(s_kc_w);
 
       unsigned long long n_ev = 0, n_mv = 0;
       int errbits = 0;
       uint32_t mask = 0;
       if (active) {
-        const double inv_nav = 1.0 / nav;
-        double a[RMAX];
+        // counts as one vector value (uniform species indices select
+        // registers); c_r = k N_A V, k or k / (N_A V) by reaction order
+        int __attribute__((ext_vector_type(SMAX))) Nv;
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r)
-          a[r] = r < R ? propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav) : 0.0;
+        for (int s = 0; s < SMAX; ++s) Nv[s] = N[s];
+        const double inv_nav = 1.0 / nav;
+        double c[RMAX], a[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          const int order = r < R ? (A.info[r] & 0xff) : 1;
+          const double kr = r < R ? s_kc[reg][r] : 0.0;
+          c[r] = order == 0 ? kr * nav : (order == 1 ? kr : kr * inv_nav);
+        }
+        all_propensities<SMAX, RMAX>(A, R, c, Nv, a);
 
         // ---- reaction SSA operator over [0, tau_k] ----
+        // Every propensity is recomputed after an event (the values of those
+        // an event cannot change are the same), and the occupancy of every
+        // species is updated through selects: no per-lane branches.
         double O[SMAX], tS[SMAX];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
@@ -876,23 +913,23 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
           if (dt + t_reac > tau) break;
           const int rn = cr_select<RMAX>(a, R, a0, st);
           dt = dt + t_reac;
+          const uint4 drow = reinterpret_cast<const uint4*>(s_delta_w)[rn];
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) {
             if (s < S) {
-              const int d = s_delta[rn][s];
-              if (d != 0) {
-                O[s] = O[s] + (double)N[s] * (dt - tS[s]);
-                tS[s] = dt;
-                touched |= 1u << s;
-                N[s] += d;
-                if (N[s] > kCountCap) errbits |= kErrOverflow;
-              }
+              const uint32_t wd = (s >> 2) == 0 ? drow.x : ((s >> 2) == 1 ? drow.y : ((s >> 2) == 2 ? drow.z : drow.w));
+              const int d = (int)(int8_t)((wd >> (8 * (s & 3))) & 0xffu);
+              const bool ch = d != 0;
+              const int n = Nv[s];
+              const double o_new = O[s] + (double)n * (dt - tS[s]);
+              O[s] = ch ? o_new : O[s];
+              tS[s] = ch ? dt : tS[s];
+              touched |= (uint32_t)ch << s;
+              Nv[s] = n + d;
+              if (ch && n + d > kCountCap) errbits |= kErrOverflow;
             }
           }
-          const unsigned long long dep = s_deps[rn];
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r)
-            if (r < R && ((dep >> r) & 1ull)) a[r] = propensity<SMAX>(M, r, s_kc[reg][r], N, nav, inv_nav);
+          all_propensities<SMAX, RMAX>(A, R, c, Nv, a);
           ++ev_tet;
           if (errbits) break;
           if (ev_tet >= (unsigned int)kEventCap) {
@@ -910,19 +947,15 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
           if (s >= S) continue;
-          double nbar;
-          if ((touched >> s) & 1u) {
-            O[s] = O[s] + (double)N[s] * (tau - tS[s]);
-            nbar = O[s] / tau;
-          } else {
-            nbar = (double)N[s];
-          }
-          if (s_td[s] > 0.0 && ga.x > 0.0 && nbar > 0.0) {
+          const int n = Nv[s];
+          const double occ = (O[s] + (double)n * (tau - tS[s])) / tau;
+          const double nbar = ((touched >> s) & 1u) ? occ : (double)n;
+          if (((dmask >> s) & 1u) && ga.x > 0.0 && nbar > 0.0) {
             mask |= 1u << s;
             s_nbar[s][lane] = nbar;
-            s_npost[s][lane] = N[s];
-          } else if (N[s] != 0) {
-            atomicAdd(cc.cout + (size_t)s * T + i, N[s]);  // nothing can leave
+            s_npost[s][lane] = n;
+          } else if (n != 0) {
+            atomicAdd(cc.cout + (size_t)s * T + i, n);  // nothing can leave
           }
         }
       }
