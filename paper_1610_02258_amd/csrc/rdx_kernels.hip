@@ -196,14 +196,6 @@ __device__ __forceinline__ int exp_field(double a) {
   return (int)((__double_as_longlong(a) >> 52) & 0x7ff);
 }
 
-template <int SMAX>
-__device__ __forceinline__ int select_count(const int (&N)[SMAX], int s) {
-  int v = 0;
-#pragma unroll
-  for (int j = 0; j < SMAX; ++j) v = (j == s) ? N[j] : v;
-  return v;
-}
-
 // a_r = c_r h_r(N): c = k N_A V[L] (order 0), k (order 1), k / (N_A V[L])
 // (order 2); h = 1, N_A, N_A N_B or N_A (N_A - 1) / 2.  Values below 2^-1000
 // are taken as zero.  `info` is the packed reaction entry (uniform).
@@ -229,35 +221,28 @@ __device__ __forceinline__ double mass_action(int info, double k, int n0, int n1
   return a >= 0x1p-1000 ? a : 0.0;
 }
 
-template <int SMAX>
-__device__ __forceinline__ double propensity(const __attribute__((address_space(4))) DevModel* M, int r, double k,
-                                             const int (&N)[SMAX], double nav, double inv_nav) {
-  const int info = M->info[r];
-  const int n0 = select_count<SMAX>(N, (info >> 8) & 0xff);
-  const int n1 = select_count<SMAX>(N, (info >> 16) & 0xff);
-  return mass_action(info, k, n0, n1, nav, inv_nav);
-}
-
 // Composition: groups of reactions with equal binary exponent, visited from
 // the largest exponent down, picked with probability proportional to their
 // totals; rejection: a uniform member is accepted with probability a / 2^g.
+// The exponent fields are taken once (absent reactions as -1); group totals
+// are summed in reaction order.
 template <int RMAX>
 __device__ int cr_select(const double (&a)[RMAX], int R, double a0, Draw53& st) {
+  int E[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) E[r] = (r < R && a[r] > 0.0) ? exp_field(a[r]) : -1;
   double x = st.co() * a0;
   int gprev = 4096, chosen = -1;
   for (;;) {
     int gcur = -1;
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
-      if (r < R && a[r] > 0.0) {
-        const int E = exp_field(a[r]);
-        if (E < gprev && E > gcur) gcur = E;
-      }
+      if (E[r] < gprev && E[r] > gcur) gcur = E[r];
     if (gcur < 0) break;
     double sum = 0.0;
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
-      if (r < R && a[r] > 0.0 && exp_field(a[r]) == gcur) sum = sum + a[r];
+      if (E[r] == gcur) sum = sum + a[r];
     chosen = gcur;
     if (x < sum) break;
     x = x - sum;
@@ -265,8 +250,7 @@ __device__ int cr_select(const double (&a)[RMAX], int R, double a0, Draw53& st) 
   }
   int n = 0;
 #pragma unroll
-  for (int r = 0; r < RMAX; ++r)
-    if (r < R && a[r] > 0.0 && exp_field(a[r]) == chosen) ++n;
+  for (int r = 0; r < RMAX; ++r) n += E[r] == chosen;
   const double bound = __longlong_as_double((long long)(chosen + 1) << 52);
   for (;;) {
     const double u2 = st.co();
@@ -277,7 +261,7 @@ __device__ int cr_select(const double (&a)[RMAX], int R, double a0, Draw53& st) 
     int rj = 0, seen = 0;
 #pragma unroll
     for (int r = 0; r < RMAX; ++r)
-      if (r < R && a[r] > 0.0 && exp_field(a[r]) == chosen) {
+      if (E[r] == chosen) {
         if (seen == j) {
           aj = a[r];
           rj = r;
@@ -749,15 +733,18 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
 }
 
-// a_r = c_r h_r(N) for every reaction, h by the reaction's order from the
-// packed (uniform) reaction entry; values below 2^-1000 are taken as zero.
+// a_r = c_r h_r(N) for the reactions in `which`, h by the reaction's order
+// from the packed (uniform) reaction entry; values below 2^-1000 are taken as
+// zero.
 template <int SMAX, int RMAX, typename NV>
-__device__ __forceinline__ void all_propensities(const StepArgs& A, int R, const double (&c)[RMAX], const NV& N,
-                                                 double (&a)[RMAX]) {
+__device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const double (&c)[RMAX], const NV& N,
+                                                double (&a)[RMAX], unsigned long long which) {
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
-    double v = 0.0;
-    if (r < R) {
+    if (r >= R) {
+      a[r] = 0.0;
+    } else if ((which >> r) & 1ull) {
+      double v;
       const int info = A.info[r];
       const int order = info & 0xff;
       const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
@@ -769,9 +756,8 @@ __device__ __forceinline__ void all_propensities(const StepArgs& A, int R, const
       else if (s0 == s1) h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
       else h = (double)n0 * (double)n1;
       v = c[r] * h;
-      v = v >= 0x1p-1000 ? v : 0.0;
+      a[r] = v >= 0x1p-1000 ? v : 0.0;
     }
-    a[r] = v;
   }
 }
 
@@ -785,6 +771,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
   // net changes (copied whole from the device model) and the rate
   // constants of the tile's run by region, filled with one round of loads
   __shared__ uint32_t s_delta_w[32 * 16 / 4];   // int8 [32][16]
+  __shared__ uint32_t s_deps_w[32 * 2];         // uint64 [32]: reactions whose propensity a reaction changes
   __shared__ uint32_t s_kc_w[kMaxRegions * 32 * 2];  // double [8][32]
   __shared__ double s_td[SMAX];               // tau_k D_s of the tile's run
   __shared__ double s_nbar[SMAX][kWave];      // mean occupancy of item (lane, s)
@@ -840,12 +827,13 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       const bool regions = rd->region != nullptr;
       const cptr<uint32_t> mw = as_const(reinterpret_cast<const uint32_t*>(A.model));
       const cptr<uint32_t> kw = as_const(reinterpret_cast<const uint32_t*>(rd->kcst));
-      uint32_t d0 = 0, d1 = 0, kv[kMaxRegions];
+      uint32_t d0 = 0, d1 = 0, dp = 0, kv[kMaxRegions];
       double dv = 0.0;
       int reg = 0;
       if (need_tables) {
         d0 = mw[offsetof(DevModel, delta) / 4 + lane];
         d1 = mw[offsetof(DevModel, delta) / 4 + kWave + lane];
+        dp = mw[offsetof(DevModel, deps) / 4 + lane];
       }
       if (need_run) {
 #pragma unroll
@@ -856,6 +844,7 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       if (need_tables) {
         s_delta_w[lane] = d0;
         s_delta_w[kWave + lane] = d1;
+        s_deps_w[lane] = dp;
         tables = true;
       }
       if (need_run) {
@@ -886,12 +875,9 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
           const double kr = r < R ? s_kc[reg][r] : 0.0;
           c[r] = order == 0 ? kr * nav : (order == 1 ? kr : kr * inv_nav);
         }
-        all_propensities<SMAX, RMAX>(A, R, c, Nv, a);
+        propensities_of<SMAX, RMAX>(A, R, c, Nv, a, ~0ull);
 
         // ---- reaction SSA operator over [0, tau_k] ----
-        // Every propensity is recomputed after an event (the values of those
-        // an event cannot change are the same), and the occupancy of every
-        // species is updated through selects: no per-lane branches.
         double O[SMAX], tS[SMAX];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
@@ -913,23 +899,26 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
           if (dt + t_reac > tau) break;
           const int rn = cr_select<RMAX>(a, R, a0, st);
           dt = dt + t_reac;
+          // few lanes of a wave are in the loop at a time, so branches that
+          // skip unchanged species and unaffected reactions are cheap
           const uint4 drow = reinterpret_cast<const uint4*>(s_delta_w)[rn];
+          const unsigned long long dep = reinterpret_cast<const unsigned long long*>(s_deps_w)[rn];
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) {
             if (s < S) {
               const uint32_t wd = (s >> 2) == 0 ? drow.x : ((s >> 2) == 1 ? drow.y : ((s >> 2) == 2 ? drow.z : drow.w));
               const int d = (int)(int8_t)((wd >> (8 * (s & 3))) & 0xffu);
-              const bool ch = d != 0;
-              const int n = Nv[s];
-              const double o_new = O[s] + (double)n * (dt - tS[s]);
-              O[s] = ch ? o_new : O[s];
-              tS[s] = ch ? dt : tS[s];
-              touched |= (uint32_t)ch << s;
-              Nv[s] = n + d;
-              if (ch && n + d > kCountCap) errbits |= kErrOverflow;
+              if (d != 0) {
+                const int n = Nv[s];
+                O[s] = O[s] + (double)n * (dt - tS[s]);
+                tS[s] = dt;
+                touched |= 1u << s;
+                Nv[s] = n + d;
+                if (n + d > kCountCap) errbits |= kErrOverflow;
+              }
             }
           }
-          all_propensities<SMAX, RMAX>(A, R, c, Nv, a);
+          propensities_of<SMAX, RMAX>(A, R, c, Nv, a, dep);
           ++ev_tet;
           if (errbits) break;
           if (ev_tet >= (unsigned int)kEventCap) {
