@@ -154,6 +154,8 @@ Engine::~Engine() {
   (void)hipFree(d_n_tiles_);
   (void)hipFree(d_base_);
   (void)hipFree(wl_tile_count_);
+  (void)hipFree(evq_);
+  (void)hipFree(evq_count_);
   (void)hipFree(wl_tet_);
   (void)hipFree(wl_reg_);
   (void)hipFree(wl_cnt_);
@@ -180,16 +182,17 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   max_tets_ = max_tets;
   max_tiles_ = (max_tets + 63) / 64 + max_runs;
   if (max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "too many tiles");
-  // one block per tile up to 16384 tiles: a tile with listed tets then has a
-  // wave of its own (the SSA chains are latency-bound), and a block whose
-  // tiles have none ends at once
-  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>(max_tiles_, 16384));
+  // event kernel: up to 2048 blocks (resident at once), one per queued tile
+  // as long as at most that many tiles have listed tets (the SSA chains are
+  // latency-bound, so every tile gets a wave of its own)
+  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>(max_tiles_, 2048));
   if (64 * max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "worklist too large");
   const size_t W = 64 * (size_t)max_tiles_;  // 64 worklist slots per tile
   bool ok = dev_alloc(&model_, 1) == hipSuccess && dev_alloc(&d_runs_, (size_t)max_runs) == hipSuccess &&
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
-            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
+            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess &&
+            dev_alloc(&evq_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&evq_count_, 2) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
             dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
             dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
@@ -207,6 +210,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
+  RDX_HIP(hipMemset(evq_count_, 0, 2 * sizeof(int32_t)));
   RDX_HIP(hipDeviceSynchronize());
   return RDX_OK;
 }
@@ -514,6 +518,8 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.model = model_;
   std::memcpy(a.info, model_host_.info, sizeof a.info);
   a.wl_tile_count = wl_tile_count_;
+  a.evq = evq_;
+  a.evq_count = evq_count_;
   a.wl_tet = wl_tet_;
   a.wl_reg = wl_reg_;
   a.wl_cnt = wl_cnt_;

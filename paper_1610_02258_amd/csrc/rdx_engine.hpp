@@ -171,6 +171,8 @@ class Engine {
   int32_t* d_n_tiles_ = nullptr;
   int32_t* d_base_ = nullptr;
   int32_t* wl_tile_count_ = nullptr;
+  int32_t* evq_ = nullptr;
+  int32_t* evq_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
   uint8_t* wl_reg_ = nullptr;
   int32_t* wl_cnt_ = nullptr;

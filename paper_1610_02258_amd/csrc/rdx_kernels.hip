@@ -635,9 +635,13 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) n_own[s] = s_acc[s][lane];
       const double Gl = s_geo[0][lane].x;
-      // the tile's listed tets take its own worklist slots: no atomics
+      // the tile's listed tets take its own worklist slots; the tile joins
+      // the queue of the event kernel
       const unsigned long long ballot = __ballot(event);
-      if (lane == 0) A.wl_tile_count[tile] = (int)__popcll(ballot);
+      if (ballot && lane == 0) {
+        A.wl_tile_count[tile] = (int)__popcll(ballot);
+        A.evq[atomicAdd(A.evq_count + (k & 1), 1)] = tile;
+      }
       if (ballot) {
         const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
         if (event) {
@@ -722,8 +726,6 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
       }
       if (errbits) atomicOr(rd->err, errbits);
       wave_sync();  // LDS is rebuilt for the next tile
-    } else if (lane == 0) {
-      A.wl_tile_count[tile] = 0;
     }
     cc = nc;
     cur = nxt;
@@ -762,9 +764,9 @@ __device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const 
 }
 
 // Event kernel: the full SSA window (composition-rejection, occupancy) and
-// the diffusion of the listed tets.  Block b scans the tiles b, b + G,
-// b + 2G, ... (one per lane) for listed entries, so the few tiles with
-// entries spread over the blocks; a tile's entries (one run) are processed
+// the diffusion of the listed tets.  Block b takes the queued tiles b, b + G,
+// ... (the grid is sized so that every queued tile usually has a block of
+// its own, all resident at once); a tile's entries (one run) are processed
 // one per lane.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
@@ -783,22 +785,18 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
 
   const int lane = threadIdx.x;
   const int k = step_index(A);
-  const int n_tiles = *as_const(A.n_tiles);
   const int G = gridDim.x;
   const int S = A.S, R = A.R;
   bool tables = false;
   int cache_run = -1;
   uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
 
-  for (int t0 = blockIdx.x; t0 < n_tiles; t0 += kWave * G) {
-    const int tl = t0 + lane * G;
-    const int c = tl < n_tiles ? A.wl_tile_count[tl] : 0;
-    unsigned long long has = __ballot(c > 0);
-    while (has) {
-      const int b = __ffsll((long long)has) - 1;
-      has &= has - 1;
-      const int tile = t0 + b * G;
-      const int n_work = __shfl(c, b);
+  const int n_queued = A.evq_count[k & 1];
+  if (blockIdx.x == 0 && lane == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
+  for (int q = blockIdx.x; q < n_queued; q += G) {
+    {
+      const int tile = A.evq[q];
+      const int n_work = A.wl_tile_count[tile];
       const TileCtx cc = tile_ctx(A, tile, k);
       const cptr<RunDesc> rd = cc.rd;
       const int T = cc.T;

@@ -60,7 +60,9 @@ struct StepArgs {
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
   // worklist of the tets whose first SSA event falls inside the window: the
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
-  int32_t* wl_tile_count;      // [tiles]
+  int32_t* wl_tile_count;      // [tiles], valid for the tiles in the queue
+  int32_t* evq;                // [tiles] queue of the tiles with listed tets
+  int32_t* evq_count;          // [2] queue lengths by step parity
   int32_t* wl_tet;
   uint8_t* wl_reg;             // region label
   int32_t* wl_cnt;             // [S][wl_stride]
