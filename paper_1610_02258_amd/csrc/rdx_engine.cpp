@@ -154,6 +154,7 @@ Engine::~Engine() {
   (void)hipFree(d_n_tiles_);
   (void)hipFree(d_base_);
   (void)hipFree(wl_tile_count_);
+  (void)hipFree(wl_mask_);
   (void)hipFree(evq_);
   (void)hipFree(evq_count_);
   (void)hipFree(wl_tet_);
@@ -182,16 +183,12 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   max_tets_ = max_tets;
   max_tiles_ = (max_tets + 63) / 64 + max_runs;
   if (max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "too many tiles");
-  // event kernel: up to 2048 blocks (resident at once), one per queued tile
-  // as long as at most that many tiles have listed tets (the SSA chains are
-  // latency-bound, so every tile gets a wave of its own)
-  event_blocks_ = (int)std::max<int64_t>(1, std::min<int64_t>(max_tiles_, 2048));
   if (64 * max_tiles_ > (int64_t)INT32_MAX) return set_error(RDX_EINVAL, "worklist too large");
   const size_t W = 64 * (size_t)max_tiles_;  // 64 worklist slots per tile
   bool ok = dev_alloc(&model_, 1) == hipSuccess && dev_alloc(&d_runs_, (size_t)max_runs) == hipSuccess &&
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
-            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess &&
+            dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&evq_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&evq_count_, 2) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
             dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
             dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
@@ -358,16 +355,33 @@ rdx_status Engine::plan_steps(Run* r, int64_t n) {
   return RDX_OK;
 }
 
-int Engine::fast_grid_for(int64_t n_tiles, int div) const {
-  const int resident = std::max(8, fast_grid_resident(S_, R_) / std::max(1, div));
+namespace {
+// Fewest rounds of tiles `resident` blocks need, then the fewest blocks (a
+// multiple of the 8 XCDs) that still finish in that many rounds.
+int rounds_grid(int64_t n_tiles, int resident) {
+  resident = std::max(8, resident);
   if (n_tiles < 1) return 1;
-  // fewest rounds of tiles the blocks need, then the fewest blocks (a
-  // multiple of the 8 XCDs) that still finish in that many rounds
   const int64_t rounds = (n_tiles + resident - 1) / resident;
   int g = (int)((n_tiles + rounds - 1) / rounds);
   if (g >= 8) g = (g + 7) & ~7;
   if (g > resident) g = resident & ~7;
   return g > 0 ? g : 1;
+}
+}  // namespace
+
+void Engine::grids_for(int64_t n_tiles, int div, int* detect, int* main) const {
+  int rd = 0, rm = 0;
+  grid_resident(S_, R_, &rd, &rm);
+  // detect kernel: one block per tile (light blocks, many resident per SIMD,
+  // so the latency of each tile's loads is hidden by the others)
+  (void)rd;
+  *detect = (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, 1 << 24));
+  // main kernel: the diffusion blocks' grid plus room for the event blocks
+  // (one per tile with listed tets, decided on the device), within what is
+  // resident at once
+  const int res = std::max(8, rm / std::max(1, div));
+  const int reserve = std::min(256, std::max(8, res / 4));
+  *main = std::max(2, std::min(res, rounds_grid(n_tiles, res) + reserve));
 }
 
 rdx_status Engine::upload_tables(const std::vector<Run*>& active, int64_t k0, hipStream_t stream,
@@ -445,7 +459,7 @@ rdx_status Engine::launch_plain(const StepArgs& a0, int64_t K, hipStream_t strea
 
 rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t stream) {
   const int W = shape_.graph_windows;
-  const auto key = std::make_pair(W, a0.fast_grid);
+  const auto key = std::make_pair(W, a0.main_grid * 65536 + a0.detect_grid);
   auto it = graphs_.find(key);
   if (it == graphs_.end()) {
     if (graphs_.size() >= 16) free_graphs();
@@ -513,7 +527,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.step_base = d_base_;
   a.S = S_;
   a.R = R_;
-  a.event_blocks = event_blocks_;
+  a.wl_mask = wl_mask_;
   a.wl_stride = (int32_t)(64 * max_tiles_);
   a.model = model_;
   std::memcpy(a.info, model_host_.info, sizeof a.info);
@@ -528,7 +542,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.wl_geo = wl_geo_;
 
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
-    a.fast_grid = fast_grid_for(n_tiles, sh.fast_grid_div);
+    grids_for(n_tiles, sh.fast_grid_div, &a.detect_grid, &a.main_grid);
     const ExecShape keep = shape_;
     shape_ = sh;
     rdx_status r = RDX_OK;
@@ -548,7 +562,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
     const ExecShape c = candidates_[cand_next_];
     const int64_t n = std::min<int64_t>(K - done, std::max(8, 2 * c.graph_windows));
     if (c.graph_windows > 1 && n >= c.graph_windows) {  // capture outside the timed span
-      a.fast_grid = fast_grid_for(n_tiles, c.fast_grid_div);
+      grids_for(n_tiles, c.fast_grid_div, &a.detect_grid, &a.main_grid);
       const ExecShape keep = shape_;
       shape_ = c;
       st = launch_graphs(a, 0, stream);

@@ -74,7 +74,7 @@ struct Run {
   double plan_tau_last = 0.0, plan_t_after = 0.0;
 };
 
-// Launch shape of a sequence.  fast_grid_div: the all-tets grid is the
+// Launch shape of a sequence.  fast_grid_div: the main kernel's grid is its
 // resident grid divided by this (1, 2, 4); graph_windows: windows per
 // captured graph (1 = plain launches).
 struct ExecShape {
@@ -154,7 +154,7 @@ class Engine {
                            int64_t* n_tiles_out);
   rdx_status launch_plain(const StepArgs& a, int64_t K, hipStream_t stream);
   rdx_status launch_graphs(const StepArgs& a, int64_t reps, hipStream_t stream);
-  int fast_grid_for(int64_t n_tiles, int div) const;
+  void grids_for(int64_t n_tiles, int div, int* detect, int* main) const;
   void free_graphs();
 
   int S_ = 0, R_ = 0;
@@ -171,6 +171,7 @@ class Engine {
   int32_t* d_n_tiles_ = nullptr;
   int32_t* d_base_ = nullptr;
   int32_t* wl_tile_count_ = nullptr;
+  unsigned long long* wl_mask_ = nullptr;
   int32_t* evq_ = nullptr;
   int32_t* evq_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
@@ -179,7 +180,6 @@ class Engine {
   double* wl_nav_ = nullptr;
   int32_t* wl_nbr_ = nullptr;
   double* wl_geo_ = nullptr;
-  int event_blocks_ = 1;
 
   // pinned staging of the run table and tile map; `staged_` marks the
   // completion of the last upload from them
@@ -191,7 +191,7 @@ class Engine {
   std::vector<int64_t> tile_run_T_;
   int64_t k_now_ = 0;                  // batch step index == *d_base_
 
-  // graphs by (windows, grid); captured on a private stream
+  // graphs by (windows, grids); captured on a private stream
   hipStream_t capture_stream_ = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
 

@@ -280,18 +280,19 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 // ------------------------------------------------------- window kernels ----
 // A window of a batch is two launches, one wave (64 lanes) per block, one lane
-// per tet.
+// per tet, 64 tets per tile (a tile belongs to one run).
 //
-// window_fast_kernel, over all tiles of all runs taking part in the step:
-// every global load of a tet is issued up front (counts, N_A V, neighbours,
-// couplings), the next tile's before the current tile is worked on; the
-// propensities and their sum a0 use uniform reaction tables (scalar loads);
-// the first SSA waiting time is drawn.  A tet whose first event falls inside
-// the window is appended to a worklist with its data; for every other tet no
-// count changes, the mean occupancy is the count itself, and its diffusion
-// items are sampled here.  window_event_kernel then runs the full SSA
-// (composition-rejection, occupancy) and the diffusion of the listed tets
-// only, so the heavy per-tet SSA state never weighs on the all-tets pass.
+// window_detect_kernel, over all tiles: the propensities and their sum a0,
+// and the tet's first SSA waiting time.  A tet whose first event falls inside
+// the window is listed (its counts and mesh data go to the tile's worklist
+// slots, the tile to a queue); a per-tile bit mask marks the listed tets.
+//
+// window_main_kernel: its first blocks take the queued tiles and run the full
+// SSA window (composition-rejection, occupancy) and the diffusion of the
+// listed tets; the other blocks walk all tiles and do the diffusion of every
+// tet that is not listed (no count changes, the mean occupancy is the count
+// itself).  The serial SSA chains of the few listed tets so run alongside the
+// bandwidth-bound diffusion of the rest instead of after it.
 //
 // Diffusion items: every (tet, species) pair with something to sample becomes
 // an item; a wave-level prefix sum over the lanes' item counts packs them into
@@ -509,21 +510,29 @@ __device__ __forceinline__ int step_index(const StepArgs& A) {
   return (A.step_base ? *as_const(A.step_base) : 0) + A.k_rel;
 }
 
-// Persistent: each block (one wave) walks its tiles of 64 tets.  Per tile:
-// (1) the counts (in registers) give the propensities and a0; the tile's data
-// moves to LDS; (2) the next tile's loads are issued, so that they are in
-// flight during the rest; (3) the first SSA waiting time, the worklist, the
-// diffusion items and the flush.  Values that depend only on the run (rate
-// constants, tau_k D_s, the key) are fetched once per run change, not per
-// tile: a persistent block's tiles mostly belong to one run.
+// What the detect kernel reads for one lane's tet.
+template <int SMAX>
+struct TetCounts {
+  int __attribute__((ext_vector_type(SMAX))) N;  // a uniform species index selects a register
+  double nav;
+  int reg;
+};
+
+template <int SMAX>
+__device__ __forceinline__ void load_counts(const TileCtx& c, int S, int i, TetCounts<SMAX>& d) {
+  const bool active = c.active && i < c.T;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) d.N[s] = (active && s < S) ? c.cin[(size_t)s * c.T + i] : 0;
+  d.nav = active ? as_const(c.rd->nav)[i] : 1.0;
+  d.reg = (active && c.rd->region) ? (int)as_const(c.rd->region)[i] : 0;
+}
+
+// Persistent: each block walks its tiles, the next tile's loads in flight
+// while the current one is worked on.  Values that depend only on the run
+// (rate constants, the key) are fetched once per run change.
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
-  __shared__ int s_acc[SMAX][kWave];         // counts, then next counts of own tets
-  __shared__ double s_tauD[SMAX];            // tau_k D_s of the current run
-  __shared__ uint32_t s_item[SMAX * kWave];  // packed items: count << 10 | lane << 4 | species
-  __shared__ int4 s_nbr[kWave];
-  __shared__ double2 s_geo[2][kWave];        // (G, cum0), (cum1, cum2)
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the current run by region
+__global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) {
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of a run with regions
 
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
@@ -531,19 +540,165 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
   const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
   int cache_run = -1;
-  unsigned long long n_moved = 0;
-  // per-run constants (uniform)
-  uint32_t key0 = 0, key1 = 0, dmask = 0;
+  uint32_t key0 = 0, key1 = 0;
   bool regions = false;
   double kc0[RMAX];
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) kc0[r] = 0.0;
 
   TileCtx cc, nc;
+  TetCounts<SMAX> cur, nxt;
+  if (tr.first < tr.end) {
+    cc = tile_ctx(A, tr.first, k);
+    load_counts<SMAX>(cc, S, cc.base + lane, cur);
+  }
+  nc = cc;
+
+  for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
+    const bool has_next = tile + tr.stride < tr.end;
+    const bool run_active = cc.active;
+    const cptr<RunDesc> rd = cc.rd;
+    const int i = cc.base + lane;
+    const bool active = i < cc.T;
+    if (run_active && cc.run != cache_run) {
+      key0 = rd->key0;
+      key1 = rd->key1;
+      regions = rd->region != nullptr;
+      const cptr<double> kc = as_const(rd->kcst);
+#pragma unroll
+      for (int r = 0; r < RMAX; ++r) kc0[r] = r < R ? kc[r] : 0.0;
+      if (regions)
+        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
+      cache_run = cc.run;
+      wave_sync();
+    }
+
+    // propensities a_r = c_r h_r(N), summed in reaction order
+    const double nav = cur.nav;
+    const int reg = cur.reg;
+    const auto Nc = cur.N;
+    double a0 = 0.0;
+    if (run_active) {
+      const double inv_nav = 1.0 / nav;
+      // two copies of the loop on the uniform region flag: rate constants
+      // from scalar registers, or per lane from LDS
+      auto sum = [&](auto with_regions) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+          if (r < R) {
+            const int info = A.info[r];
+            double kr;
+            if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
+            else kr = kc0[r];
+            const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+            const int n0 = s0 < SMAX ? Nc[s0] : 0;
+            const int n1 = s1 < SMAX ? Nc[s1] : 0;
+            acc = acc + mass_action(info, kr, n0, n1, nav, inv_nav);
+          }
+        }
+        return acc;
+      };
+      a0 = regions ? sum(std::true_type{}) : sum(std::false_type{});
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (has_next) {
+      nc = tile_ctx(A, tile + tr.stride, k);
+      load_counts<SMAX>(nc, S, nc.base + lane, nxt);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // first waiting time: does an event fall inside the window?  Since
+    // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
+    // margin, far above the rounding of ln and of the division) certainly
+    // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
+    bool event = false;
+    if (run_active && active && a0 > 0.0) {
+      Draw53 st(key0, key1, 0u, (uint32_t)i, cc.window);
+      const double u = st.oc();
+      if (!(1.0 - u > (cc.tau_k * a0) * 1.0000001)) {
+        const double t_reac = -ln_basic(u) / a0;
+        event = !(0.0 + t_reac > cc.tau_k);
+      }
+    }
+    const unsigned long long ballot = __ballot(event);
+    if (lane == 0) {
+      A.wl_mask[tile] = ballot;
+      if (ballot) {
+        A.wl_tile_count[tile] = (int)__popcll(ballot);
+        A.evq[atomicAdd(A.evq_count + (k & 1), 1)] = tile;
+      }
+    }
+    if (event) {  // the tile's listed tets take its own worklist slots
+      const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
+      A.wl_tet[slot] = i;
+      A.wl_nav[slot] = nav;
+      A.wl_reg[slot] = (uint8_t)reg;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = Nc[s];
+      reinterpret_cast<int4*>(A.wl_nbr)[slot] = ld_int4(reinterpret_cast<const int4*>(rd->nbr), (size_t)i);
+      reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i);
+      reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] =
+          ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i + 1);
+    }
+    cc = nc;
+    cur = nxt;
+  }
+}
+
+// LDS of the main kernel: a block is either a diffusion block or an event
+// block, so the two layouts share the space.
+template <int SMAX>
+struct DiffusionLds {
+  int acc[SMAX][kWave];         // counts, then next counts of own tets
+  double tauD[SMAX];            // tau_k D_s of the current run
+  uint32_t item[SMAX * kWave];  // packed items: count << 10 | lane << 4 | species
+  int4 nbr[kWave];
+  double2 geo[2][kWave];        // (G, cum0), (cum1, cum2)
+};
+
+template <int SMAX>
+struct EventLds {
+  // net changes and dependencies (copied whole from the device model) and
+  // the rate constants of the tile's run by region
+  uint32_t delta_w[32 * 16 / 4];        // int8 [32][16]
+  uint32_t deps_w[32 * 2];              // uint64 [32]: reactions whose propensity a reaction changes
+  uint32_t kc_w[kMaxRegions * 32 * 2];  // double [8][32]
+  double td[SMAX];                      // tau_k D_s of the tile's run
+  double nbar[SMAX][kWave];             // mean occupancy of item (lane, s)
+  int npost[SMAX][kWave];               // post-reaction count of item (lane, s)
+  uint16_t item[SMAX * kWave];          // packed items: lane << 4 | species
+  int4 nbr[kWave];
+  double2 geo[2][kWave];                // (G, cum0), (cum1, cum2)
+  int tet[kWave];
+};
+
+template <int SMAX>
+union MainLds {
+  DiffusionLds<SMAX> d;
+  EventLds<SMAX> e;
+};
+
+// Diffusion blocks (b of G): the tets not listed, tile by tile, persistent,
+// the next tile's loads in flight while the current one is worked on.
+template <int SMAX, int RMAX>
+__device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, int G, DiffusionLds<SMAX>& L) {
+  const int lane = threadIdx.x;
+  const int S = A.S;
+  const int n_tiles = *as_const(A.n_tiles);
+  const TileRange tr = tile_range(b, G, n_tiles);
+  int cache_run = -1;
+  unsigned long long n_moved = 0;
+  uint32_t key0 = 0, key1 = 0, dmask = 0;  // per-run constants (uniform)
+
+  TileCtx cc, nc;
   TetData<SMAX> cur, nxt;
+  unsigned long long cmask = 0, nmask = 0;  // listed tets of the tile
   if (tr.first < tr.end) {
     cc = tile_ctx(A, tr.first, k);
     load_tet<SMAX>(cc, S, cc.base + lane, cur);
+    cmask = as_const(A.wl_mask)[tr.first];
   }
   nc = cc;
 
@@ -562,102 +717,36 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
       }
       key0 = rd->key0;
       key1 = rd->key1;
-      regions = rd->region != nullptr;
-      const cptr<double> kc = as_const(rd->kcst);
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r) kc0[r] = r < R ? kc[r] : 0.0;
-      if (regions)
-        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
       const double d = lane < S ? rd->D[lane < SMAX ? lane : 0] : 0.0;
-      if (lane < SMAX) s_tauD[lane] = lane < S ? cc.tau_k * d : 0.0;
+      if (lane < SMAX) L.tauD[lane] = lane < S ? cc.tau_k * d : 0.0;
       dmask = (uint32_t)__ballot(lane < S && d > 0.0);
       cache_run = cc.run;
-      wave_sync();
     }
-
-    // (1) propensities a_r = c_r h_r(N) from the counts in registers, summed
-    // in reaction order; reactant species are uniform register indices
-    const double nav = cur.nav;
-    const int reg = cur.reg;
-    double a0 = 0.0;
-    if (run_active) {
-      const double inv_nav = 1.0 / nav;
-      // two copies of the loop on the uniform region flag: rate constants
-      // from scalar registers, or per lane from LDS
-      auto sum = [&](auto with_regions) {
-        double acc = 0.0;
+    // the tile's data moves from registers to LDS before the next tile's
+    // loads are issued, so that waiting for this tile's loads never waits for
+    // the next tile's (an inactive tile's data is all zero)
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-          if (r < R) {
-            const int info = A.info[r];
-            double kr;
-            if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
-            else kr = kc0[r];
-            const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-            const int n0 = s0 < SMAX ? cur.N[s0] : 0;
-            const int n1 = s1 < SMAX ? cur.N[s1] : 0;
-            acc = acc + mass_action(info, kr, n0, n1, nav, inv_nav);
-          }
-        }
-        return acc;
-      };
-      a0 = regions ? sum(std::true_type{}) : sum(std::false_type{});
-    }
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) s_acc[s][lane] = cur.N[s];
-    s_nbr[lane] = cur.nb;
-    s_geo[0][lane] = cur.ga;
-    s_geo[1][lane] = cur.gb;
+    for (int s = 0; s < SMAX; ++s) L.acc[s][lane] = cur.N[s];
+    L.nbr[lane] = cur.nb;
+    L.geo[0][lane] = cur.ga;
+    L.geo[1][lane] = cur.gb;
+    const bool event = (cmask >> lane) & 1ull;
     wave_sync();
-    // (2) the next tile's loads
     __builtin_amdgcn_sched_barrier(0);
     if (has_next) {
       nc = tile_ctx(A, tile + tr.stride, k);
       load_tet<SMAX>(nc, S, nc.base + lane, nxt);
+      nmask = as_const(A.wl_mask)[tile + tr.stride];
     }
     __builtin_amdgcn_sched_barrier(0);
 
     if (run_active) {
-      // (3) first waiting time: does an event fall inside the window?  Since
-      // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
-      // margin, far above the rounding of ln and of the division) certainly
-      // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
-      bool event = false;
-      if (active && a0 > 0.0) {
-        Draw53 st(key0, key1, 0u, (uint32_t)i, cc.window);
-        const double u = st.oc();
-        if (!(1.0 - u > (cc.tau_k * a0) * 1.0000001)) {
-          const double t_reac = -ln_basic(u) / a0;
-          event = !(0.0 + t_reac > cc.tau_k);
-        }
-      }
       int n_own[SMAX];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) n_own[s] = s_acc[s][lane];
-      const double Gl = s_geo[0][lane].x;
-      // the tile's listed tets take its own worklist slots; the tile joins
-      // the queue of the event kernel
-      const unsigned long long ballot = __ballot(event);
-      if (ballot && lane == 0) {
-        A.wl_tile_count[tile] = (int)__popcll(ballot);
-        A.evq[atomicAdd(A.evq_count + (k & 1), 1)] = tile;
-      }
-      if (ballot) {
-        const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
-        if (event) {
-          A.wl_tet[slot] = i;
-          A.wl_nav[slot] = nav;
-          A.wl_reg[slot] = (uint8_t)reg;
-          reinterpret_cast<int4*>(A.wl_nbr)[slot] = s_nbr[lane];
-          reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = s_geo[0][lane];
-          reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] = s_geo[1][lane];
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s)
-            if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = n_own[s];
-        }
-      }
+      for (int s = 0; s < SMAX; ++s) n_own[s] = L.acc[s][lane];
+      const double Gl = L.geo[0][lane].x;
 
-      // no event: Nbar = N; items for the diffusion operator
+      // a listed tet is left to the event blocks; for the others Nbar = N
       uint32_t mask = 0;
       if (active && !event && Gl > 0.0) {
 #pragma unroll
@@ -675,32 +764,32 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
         if (n > kCountCap) errbits |= kErrOverflow;
         if ((mask >> s) & 1u) {
           // a count of 2^22 or more does not fit the packed field (0 marks it)
-          s_item[pos++] = ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
+          L.item[pos++] = ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
         }
         // the accumulator starts with what cannot leave
-        s_acc[s][lane] = ((mask >> s) & 1u) || event || !active ? 0 : n;
+        L.acc[s][lane] = ((mask >> s) & 1u) || event || !active ? 0 : n;
       }
       wave_sync();
 
       const int base = cc.base;
       for (int j = lane; j < total; j += kWave) {
-        const uint32_t it = s_item[j];
-        const int L = (int)((it >> 4) & 63);
+        const uint32_t it = L.item[j];
+        const int Ln = (int)((it >> 4) & 63);
         const int sp = (int)(it & 15);
         int m = (int)(it >> 10);
-        if (m == 0) m = cc.cin[(size_t)sp * T + base + L];  // an unpacked large count
-        const int4 tnb = s_nbr[L];
-        const double2 ga = s_geo[0][L], gb = s_geo[1][L];
-        const double tds = s_tauD[sp];
-        const ItemMoves mv = sample_item(key0, key1, cc.window, base + L, sp, (double)m, m, tnb, ga, gb, tds);
+        if (m == 0) m = cc.cin[(size_t)sp * T + base + Ln];  // an unpacked large count
+        const int4 tnb = L.nbr[Ln];
+        const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
+        const double tds = L.tauD[sp];
+        const ItemMoves mv = sample_item(key0, key1, cc.window, base + Ln, sp, (double)m, m, tnb, ga, gb, tds);
         // own remainder and moves to the tile's own tets go to LDS, the rest
         // to the next count buffer
         int32_t* __restrict__ out_s = cc.cout + (size_t)sp * T;
-        if (m != mv.n) atomicAdd(&s_acc[sp][L], m - mv.n);
+        if (m != mv.n) atomicAdd(&L.acc[sp][Ln], m - mv.n);
 #define RDX_DEPOSIT(t, v)                                               \
         if (v) {                                                        \
           const unsigned off = (unsigned)((t) - base);                   \
-          if (off < (unsigned)kWave) atomicAdd(&s_acc[sp][off], (v));    \
+          if (off < (unsigned)kWave) atomicAdd(&L.acc[sp][off], (v));    \
           else atomicAdd(out_s + (t), (v));                              \
         }
         RDX_DEPOSIT(tnb.x, mv.o0)
@@ -714,7 +803,7 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
       // coalesced flush of the tile's own tets (other tiles add into them too)
       int v[SMAX];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) v[s] = s_acc[s][lane];
+      for (int s = 0; s < SMAX; ++s) v[s] = L.acc[s][lane];
       if (active) {
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
@@ -725,10 +814,11 @@ __global__ void __launch_bounds__(kWave) window_fast_kernel(const StepArgs A) {
         }
       }
       if (errbits) atomicOr(rd->err, errbits);
-      wave_sync();  // LDS is rebuilt for the next tile
     }
+    wave_sync();  // LDS is rebuilt for the next tile
     cc = nc;
     cur = nxt;
+    cmask = nmask;
   }
 
   const unsigned long long mv = wave_sum(n_moved);
@@ -763,37 +853,17 @@ __device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const 
   }
 }
 
-// Event kernel: the full SSA window (composition-rejection, occupancy) and
-// the diffusion of the listed tets.  Block b takes the queued tiles b, b + G,
-// ... (the grid is sized so that every queued tile usually has a block of
-// its own, all resident at once); a tile's entries (one run) are processed
-// one per lane.
+// Event blocks (b of E): the queued tiles b, b + E, ...; a tile's listed
+// tets (one run) one per lane.
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
-  // net changes (copied whole from the device model) and the rate
-  // constants of the tile's run by region, filled with one round of loads
-  __shared__ uint32_t s_delta_w[32 * 16 / 4];   // int8 [32][16]
-  __shared__ uint32_t s_deps_w[32 * 2];         // uint64 [32]: reactions whose propensity a reaction changes
-  __shared__ uint32_t s_kc_w[kMaxRegions * 32 * 2];  // double [8][32]
-  __shared__ double s_td[SMAX];               // tau_k D_s of the tile's run
-  __shared__ double s_nbar[SMAX][kWave];      // mean occupancy of item (lane, s)
-  __shared__ int s_npost[SMAX][kWave];        // post-reaction count of item (lane, s)
-  __shared__ uint16_t s_item[SMAX * kWave];   // packed items: lane << 4 | species
-  __shared__ int4 s_nbr[kWave];
-  __shared__ double2 s_geo[2][kWave];         // (G, cum0), (cum1, cum2)
-  __shared__ int s_tet[kWave];
-
+__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued, EventLds<SMAX>& L) {
   const int lane = threadIdx.x;
-  const int k = step_index(A);
-  const int G = gridDim.x;
   const int S = A.S, R = A.R;
   bool tables = false;
   int cache_run = -1;
   uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
 
-  const int n_queued = A.evq_count[k & 1];
-  if (blockIdx.x == 0 && lane == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
-  for (int q = blockIdx.x; q < n_queued; q += G) {
+  for (int q = b; q < n_queued; q += E) {
     {
       const int tile = A.evq[q];
       const int n_work = A.wl_tile_count[tile];
@@ -840,21 +910,21 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       }
       if (active && regions) reg = A.wl_reg[e];
       if (need_tables) {
-        s_delta_w[lane] = d0;
-        s_delta_w[kWave + lane] = d1;
-        s_deps_w[lane] = dp;
+        L.delta_w[lane] = d0;
+        L.delta_w[kWave + lane] = d1;
+        L.deps_w[lane] = dp;
         tables = true;
       }
       if (need_run) {
 #pragma unroll
         for (int q = 0; q < kMaxRegions; ++q)
-          if (q == 0 || regions) s_kc_w[q * kWave + lane] = kv[q];
-        if (lane < SMAX) s_td[lane] = lane < S ? tau * dv : 0.0;
+          if (q == 0 || regions) L.kc_w[q * kWave + lane] = kv[q];
+        if (lane < SMAX) L.td[lane] = lane < S ? tau * dv : 0.0;
         dmask = (uint32_t)__ballot(lane < SMAX && lane < S && tau * dv > 0.0);
         cache_run = cc.run;
       }
       wave_sync();
-      const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(s_kc_w);
+      const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(L.kc_w);
 
       unsigned long long n_ev = 0, n_mv = 0;
       int errbits = 0;
@@ -899,8 +969,8 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
           dt = dt + t_reac;
           // few lanes of a wave are in the loop at a time, so branches that
           // skip unchanged species and unaffected reactions are cheap
-          const uint4 drow = reinterpret_cast<const uint4*>(s_delta_w)[rn];
-          const unsigned long long dep = reinterpret_cast<const unsigned long long*>(s_deps_w)[rn];
+          const uint4 drow = reinterpret_cast<const uint4*>(L.delta_w)[rn];
+          const unsigned long long dep = reinterpret_cast<const unsigned long long*>(L.deps_w)[rn];
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) {
             if (s < S) {
@@ -927,10 +997,10 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
         n_ev = ev_tet;
 
         // ---- mean occupancies; items for the diffusion operator ----
-        s_tet[lane] = i;
-        s_nbr[lane] = nb;
-        s_geo[0][lane] = ga;
-        s_geo[1][lane] = gb;
+        L.tet[lane] = i;
+        L.nbr[lane] = nb;
+        L.geo[0][lane] = ga;
+        L.geo[1][lane] = gb;
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
           if (s >= S) continue;
@@ -939,8 +1009,8 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
           const double nbar = ((touched >> s) & 1u) ? occ : (double)n;
           if (((dmask >> s) & 1u) && ga.x > 0.0 && nbar > 0.0) {
             mask |= 1u << s;
-            s_nbar[s][lane] = nbar;
-            s_npost[s][lane] = n;
+            L.nbar[s][lane] = nbar;
+            L.npost[s][lane] = n;
           } else if (n != 0) {
             atomicAdd(cc.cout + (size_t)s * T + i, n);  // nothing can leave
           }
@@ -952,16 +1022,16 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       int pos = incl - cnt;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s)
-        if ((mask >> s) & 1u) s_item[pos++] = (uint16_t)((lane << 4) | s);
+        if ((mask >> s) & 1u) L.item[pos++] = (uint16_t)((lane << 4) | s);
       wave_sync();
       for (int j = lane; j < total; j += kWave) {
-        const int it = s_item[j];
-        const int L = it >> 4, sp = it & 15;
-        const int ti = s_tet[L];
-        const int npost = s_npost[sp][L];
-        const int4 tnb = s_nbr[L];
-        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, s_nbar[sp][L], npost,
-                                         tnb, s_geo[0][L], s_geo[1][L], s_td[sp]);
+        const int it = L.item[j];
+        const int Ln = it >> 4, sp = it & 15;
+        const int ti = L.tet[Ln];
+        const int npost = L.npost[sp][Ln];
+        const int4 tnb = L.nbr[Ln];
+        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[sp][Ln], npost,
+                                         tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
         int32_t* out_s = cc.cout + (size_t)sp * T;
         if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
         if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
@@ -979,6 +1049,25 @@ __global__ void __launch_bounds__(kWave) window_event_kernel(const StepArgs A) {
       wave_sync();  // LDS is rebuilt for the next tile
     }
   }
+}
+
+template <int SMAX, int RMAX>
+__global__ void __launch_bounds__(kWave) window_main_kernel(const StepArgs A) {
+  __shared__ MainLds<SMAX> lds;
+  const int k = step_index(A);
+  const int n_queued = __builtin_amdgcn_readfirstlane(A.evq_count[k & 1]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
+  // event blocks: one per queued tile, a multiple of the 8 XCDs (so that the
+  // diffusion blocks keep their XCD mapping), at most half the grid
+  const int G = gridDim.x;
+  int E = 0;
+  if (n_queued > 0) {
+    const int cap = G / 2 >= 8 ? (G / 2) & ~7 : (G / 2 > 0 ? G / 2 : 1);
+    E = (n_queued + 7) & ~7;
+    if (E > cap) E = cap;
+  }
+  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, lds.e);
+  else diffusion_part<SMAX, RMAX>(A, k, (int)blockIdx.x - E, G - E, lds.d);
 }
 
 __global__ void advance_base_kernel(int32_t* base, int32_t add) { *base += add; }
@@ -1020,38 +1109,56 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBloc
 
 }  // namespace
 
-// Blocks of the all-tets kernel the device holds at once (occupancy x CUs).
+// Blocks of a window kernel the device holds at once (occupancy x CUs).
+template <typename K>
+int resident_blocks_of(K kernel) {
+  int dev = 0, n_cu = 0, per_cu = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), kWave, 0);
+  return n_cu > 0 && per_cu > 0 ? n_cu * per_cu : 2048;
+}
+
 template <int SMAX, int RMAX>
-int resident_blocks() {
-  static const int resident = [] {
-    int dev = 0, n_cu = 0, per_cu = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&window_fast_kernel<SMAX, RMAX>), kWave, 0);
-    return n_cu > 0 && per_cu > 0 ? n_cu * per_cu : 2048;
-  }();
-  return resident;
+int main_resident() {
+  static const int r = resident_blocks_of(&window_main_kernel<SMAX, RMAX>);
+  return r;
+}
+
+template <int SMAX, int RMAX>
+int detect_resident() {
+  static const int r = resident_blocks_of(&window_detect_kernel<SMAX, RMAX>);
+  return r;
 }
 
 template <int SMAX, int RMAX>
 hipError_t launch_pair(const StepArgs& a, hipStream_t stream, hipEvent_t* marks) {
   if (marks) (void)hipEventRecord(marks[0], stream);
-  hipLaunchKernelGGL((window_fast_kernel<SMAX, RMAX>), dim3((unsigned)a.fast_grid), dim3(kWave), 0,
+  hipLaunchKernelGGL((window_detect_kernel<SMAX, RMAX>), dim3((unsigned)a.detect_grid), dim3(kWave), 0,
                      stream, a);
   if (marks) (void)hipEventRecord(marks[1], stream);
-  hipLaunchKernelGGL((window_event_kernel<SMAX, RMAX>), dim3((unsigned)a.event_blocks), dim3(kWave), 0,
-                     stream, a);
+  hipLaunchKernelGGL((window_main_kernel<SMAX, RMAX>), dim3((unsigned)a.main_grid), dim3(kWave), 0, stream, a);
   if (marks) (void)hipEventRecord(marks[2], stream);
   return hipGetLastError();
 }
 
-int fast_grid_resident(int S, int R) {
-  if (S <= 4 && R <= 4) return resident_blocks<4, 4>();
-  if (S <= 8 && R <= 8) return resident_blocks<8, 8>();
-  if (S <= 12 && R <= 12) return resident_blocks<12, 12>();
-  if (S <= 16 && R <= 24) return resident_blocks<16, 24>();
-  return resident_blocks<16, 32>();
+void grid_resident(int S, int R, int* detect, int* main) {
+  if (S <= 4 && R <= 4) {
+    *detect = detect_resident<4, 4>();
+    *main = main_resident<4, 4>();
+  } else if (S <= 8 && R <= 8) {
+    *detect = detect_resident<8, 8>();
+    *main = main_resident<8, 8>();
+  } else if (S <= 12 && R <= 12) {
+    *detect = detect_resident<12, 12>();
+    *main = main_resident<12, 12>();
+  } else if (S <= 16 && R <= 24) {
+    *detect = detect_resident<16, 24>();
+    *main = main_resident<16, 24>();
+  } else {
+    *detect = detect_resident<16, 32>();
+    *main = main_resident<16, 32>();
+  }
 }
 
 hipError_t launch_window(const StepArgs& a, hipStream_t stream, hipEvent_t* marks) {

@@ -53,13 +53,14 @@ struct StepArgs {
   const int32_t* step_base;    // device: step index of k_rel = 0 (nullptr: 0)
   int32_t k_rel;
   int32_t S, R;
-  int32_t fast_grid;           // persistent grid of the all-tets kernel
-  int32_t event_blocks;        // grid of the event kernel
+  int32_t detect_grid;         // persistent grid of the detect kernel
+  int32_t main_grid;           // grid of the main kernel (event blocks + persistent diffusion blocks), >= 2
   int32_t wl_stride;           // worklist capacity, 64 entries per tile (row stride of wl_cnt)
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
   // worklist of the tets whose first SSA event falls inside the window: the
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
+  unsigned long long* wl_mask; // [tiles] listed tets of each tile (bit = lane)
   int32_t* wl_tile_count;      // [tiles], valid for the tiles in the queue
   int32_t* evq;                // [tiles] queue of the tiles with listed tets
   int32_t* evq_count;          // [2] queue lengths by step parity
@@ -76,12 +77,13 @@ struct StepArgs {
 // address.
 constexpr int kTallySlots = 64;
 
-// Resident-grid size of the all-tets kernel for (S, R): occupancy x compute units.
-int fast_grid_resident(int S, int R);
+// Blocks of the detect and of the main kernel for (S, R) the device holds at
+// once (occupancy x compute units).
+void grid_resident(int S, int R, int* detect, int* main);
 
-// One window: the all-tets kernel, then the event kernel over the tets it
-// listed; the instance is picked by (S, R).  Both are enqueued on `stream`;
-// when `marks` is given, marks[0..2] are recorded before, between and after.
+// One window: the detect kernel, then the main kernel; the instance is picked
+// by (S, R).  Both are enqueued on `stream`; when `marks` is given,
+// marks[0..2] are recorded before, between and after.
 hipError_t launch_window(const StepArgs& a, hipStream_t stream, hipEvent_t* marks = nullptr);
 
 // *base += add (one thread): advances the step base at the end of a replayed
