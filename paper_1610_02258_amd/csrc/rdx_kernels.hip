@@ -532,7 +532,8 @@ __device__ __forceinline__ void load_counts(const TileCtx& c, int S, int i, TetC
 // (rate constants, the key) are fetched once per run change.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) {
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of a run with regions
+  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the current run by region
+  __shared__ int s_info[RMAX];                // packed reaction entries
 
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
@@ -541,10 +542,7 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
   int cache_run = -1;
   uint32_t key0 = 0, key1 = 0;
-  bool regions = false;
-  double kc0[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) kc0[r] = 0.0;
+  if (lane < RMAX) s_info[lane] = lane < R ? A.model->info[lane] : 0;
 
   TileCtx cc, nc;
   TetCounts<SMAX> cur, nxt;
@@ -563,12 +561,9 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     if (run_active && cc.run != cache_run) {
       key0 = rd->key0;
       key1 = rd->key1;
-      regions = rd->region != nullptr;
       const cptr<double> kc = as_const(rd->kcst);
-#pragma unroll
-      for (int r = 0; r < RMAX; ++r) kc0[r] = r < R ? kc[r] : 0.0;
-      if (regions)
-        for (int x = lane; x < kMaxRegions * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
+      const int nreg = rd->region != nullptr ? kMaxRegions : 1;
+      for (int x = lane; x < nreg * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
       cache_run = cc.run;
       wave_sync();
     }
@@ -579,27 +574,19 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     const auto Nc = cur.N;
     double a0 = 0.0;
     if (run_active) {
+      // a loop over the reactions (not unrolled): the packed entry is an LDS
+      // broadcast made uniform, its species are uniform register indices,
+      // the rate constant an LDS broadcast (or per region)
       const double inv_nav = 1.0 / nav;
-      // two copies of the loop on the uniform region flag: rate constants
-      // from scalar registers, or per lane from LDS
-      auto sum = [&](auto with_regions) {
-        double acc = 0.0;
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-          if (r < R) {
-            const int info = A.info[r];
-            double kr;
-            if constexpr (decltype(with_regions)::value) kr = s_kc[reg][r];
-            else kr = kc0[r];
-            const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-            const int n0 = s0 < SMAX ? Nc[s0] : 0;
-            const int n1 = s1 < SMAX ? Nc[s1] : 0;
-            acc = acc + mass_action(info, kr, n0, n1, nav, inv_nav);
-          }
-        }
-        return acc;
-      };
-      a0 = regions ? sum(std::true_type{}) : sum(std::false_type{});
+#pragma unroll 1
+      for (int r = 0; r < R; ++r) {
+        const int info = __builtin_amdgcn_readfirstlane(s_info[r]);
+        const double kr = s_kc[reg][r];
+        const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+        const int n0 = s0 < SMAX ? Nc[s0] : 0;
+        const int n1 = s1 < SMAX ? Nc[s1] : 0;
+        a0 = a0 + mass_action(info, kr, n0, n1, nav, inv_nav);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     if (has_next) {
