@@ -26,21 +26,27 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_02258_amd", "csrc", "rdx_kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "window_fast_kernel_simple10_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "window_main_kernel_simple10_counters.txt")
 
 
-def algorithmic_bytes(T: int, S: int, n_regions: int, molecules_moved: float) -> float:
-    """Bytes the all-tets kernel must move in one window: counts read + written
-    (8 S per tet), the neighbour ids (16), the couplings G, cum0..cum2 (32),
-    N_A V (8), the region label when the model has regions (1), and one 4-byte
-    read-modify-write per moved molecule's target count (8 each; moved
-    molecules bound the nonzero face moves from above)."""
-    per_tet = 8 * S + 16 + 32 + 8 + (1 if n_regions > 1 else 0)
-    return float(T) * per_tet + 8.0 * molecules_moved
+def main_kernel_bytes(T: int, S: int, molecules_moved: float) -> float:
+    """Bytes the main kernel must move in one window: the counts read and the
+    next counts written (8 S per tet), the neighbour ids (16), the couplings
+    G, cum0..cum2 (32), and one 4-byte read-modify-write per moved
+    molecule's target count (8 each; moved molecules bound the nonzero face
+    moves from above).  The listed tets' worklist traffic is left out (a few
+    hundred tets of 480,000)."""
+    return float(T) * (8 * S + 16 + 32) + 8.0 * molecules_moved
+
+
+def detect_kernel_bytes(T: int, S: int, n_regions: int) -> float:
+    """Bytes the detect kernel must read in one window: the counts (4 S per
+    tet), N_A V (8) and the region label when the model has regions (1)."""
+    return float(T) * (4 * S + 8 + (1 if n_regions > 1 else 0))
 
 
 def measured_traffic():
-    """HBM bytes per launch of the all-tets kernel from the committed rocprofv3
+    """HBM bytes per launch of the main kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
     calibration factor), or None if the kernel source changed since."""
     import hashlib
@@ -247,8 +253,8 @@ def main() -> int:
     torch.cuda.synchronize()
 
     # timed region: K steps.  The library records HIP events on the launch
-    # stream around each window's two kernels (all-tets kernel, SSA event
-    # kernel), which gives each kernel's average duration.
+    # stream around each window's two kernels (detect kernel, main kernel),
+    # which gives each kernel's average duration.
     sim.kernel_times(reset=True)
     sim.set_kernel_timing(True)
     torch.cuda.synchronize()
@@ -266,11 +272,12 @@ def main() -> int:
     events_total = st.ssa_events * args.steps
     moves_total = st.moves * args.steps
     launches = kt["windows"]
-    avg_launch_s = kt["all_tets_ms"] * 1e-3 / max(launches, 1)
-    avg_event_s = kt["event_ms"] * 1e-3 / max(launches, 1)
+    avg_main_s = kt["main_ms"] * 1e-3 / max(launches, 1)
+    avg_detect_s = kt["detect_ms"] * 1e-3 / max(launches, 1)
     voxel_steps = T * windows_per_step * args.steps
-    bytes_per_launch = algorithmic_bytes(T, S, n_regions, st.moves / windows_per_step)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
+    bytes_main = main_kernel_bytes(T, S, st.moves / windows_per_step)
+    bytes_detect = detect_kernel_bytes(T, S, n_regions)
+    achieved = bytes_main / avg_main_s / 1e9
     traffic = measured_traffic()
 
     out = {
@@ -295,10 +302,12 @@ def main() -> int:
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "window_fast_kernel", "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_launch": bytes_per_launch,
-                     "event_kernel_avg_us": avg_event_s * 1e6,
-                     "window_us": elapsed * 1e6 / (windows_per_step * args.steps)},
+                     "kernel": "window_main_kernel", "avg_launch_us": avg_main_s * 1e6,
+                     "bytes_per_launch": bytes_main,
+                     "detect_kernel": {"avg_launch_us": avg_detect_s * 1e6, "bytes_per_launch": bytes_detect,
+                                       "achieved_GBs": bytes_detect / avg_detect_s / 1e9},
+                     "window_us": elapsed * 1e6 / (windows_per_step * args.steps),
+                     "window_GBs": (bytes_main + bytes_detect) / (elapsed / (windows_per_step * args.steps)) / 1e9},
     }
     sim.close()
     if not args.no_batched:

@@ -153,13 +153,16 @@ rdx_status rdx_setup_geometry(const rdx_mesh* mesh, const rdx_model* model, doub
                               double* tau);
 
 /* Per-kernel device time, measured with HIP events recorded on the launch
- * stream around every window's two kernels (the all-tets kernel and the SSA
- * event kernel) while timing is enabled.  Timing adds three event records per
- * window; it is off by default. */
+ * stream around every window's two kernels while timing is enabled: the
+ * detect kernel (propensities and first SSA waiting time of every tet; lists
+ * the tets with an event in the window) and the main kernel (diffusion of
+ * every other tet, and the full SSA window and diffusion of the listed tets
+ * in blocks of their own).  Timing adds three event records per window and
+ * plain launches; it is off by default. */
 typedef struct rdx_kernel_times {
   int64_t windows;        /* windows timed since the last reset */
-  double all_tets_ms;     /* summed duration of the all-tets kernel */
-  double event_ms;        /* summed duration of the SSA event kernel */
+  double detect_ms;       /* summed duration of the detect kernel */
+  double main_ms;         /* summed duration of the main kernel */
 } rdx_kernel_times;
 
 rdx_status rdx_set_kernel_timing(rdx_sim* sim, int enable);

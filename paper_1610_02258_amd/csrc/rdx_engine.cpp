@@ -617,17 +617,17 @@ rdx_status Engine::kernel_times(rdx_kernel_times* out, bool reset) {
     float a = 0.f, b = 0.f;
     RDX_HIP(hipEventElapsedTime(&a, marks_[k], marks_[k + 1]));
     RDX_HIP(hipEventElapsedTime(&b, marks_[k + 1], marks_[k + 2]));
-    fast_ms_ += a;
-    event_ms_ += b;
+    detect_ms_ += a;
+    main_ms_ += b;
     timed_windows_ += 1;
   }
   marks_used_ = 0;
   out->windows = timed_windows_;
-  out->all_tets_ms = fast_ms_;
-  out->event_ms = event_ms_;
+  out->detect_ms = detect_ms_;
+  out->main_ms = main_ms_;
   if (reset) {
     timed_windows_ = 0;
-    fast_ms_ = event_ms_ = 0.0;
+    detect_ms_ = main_ms_ = 0.0;
   }
   return RDX_OK;
 }

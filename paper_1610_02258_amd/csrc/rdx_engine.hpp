@@ -206,7 +206,7 @@ class Engine {
   std::vector<hipEvent_t> marks_;
   size_t marks_used_ = 0;
   int64_t timed_windows_ = 0;
-  double fast_ms_ = 0.0, event_ms_ = 0.0;
+  double detect_ms_ = 0.0, main_ms_ = 0.0;
 };
 
 // DevModel of a validated instance (packed reaction entries, net changes,

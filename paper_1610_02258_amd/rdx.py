@@ -150,7 +150,7 @@ REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
 
 
 class _KernelTimes(C.Structure):
-    _fields_ = [("windows", C.c_int64), ("all_tets_ms", C.c_double), ("event_ms", C.c_double)]
+    _fields_ = [("windows", C.c_int64), ("detect_ms", C.c_double), ("main_ms", C.c_double)]
 
 
 @dataclass
@@ -295,7 +295,7 @@ class Sim:
     def kernel_times(self, reset: bool = False) -> dict:
         kt = _KernelTimes()
         _check(lib().rdx_get_kernel_times(self._h, C.byref(kt), int(bool(reset))), "rdx_get_kernel_times")
-        return dict(windows=kt.windows, all_tets_ms=kt.all_tets_ms, event_ms=kt.event_ms)
+        return dict(windows=kt.windows, detect_ms=kt.detect_ms, main_ms=kt.main_ms)
 
     def geometry(self) -> dict:
         T = self.T
