@@ -653,9 +653,9 @@ struct EventLds {
   uint32_t deps_w[32 * 2];              // uint64 [32]: reactions whose propensity a reaction changes
   uint32_t kc_w[kMaxRegions * 32 * 2];  // double [8][32]
   double td[SMAX];                      // tau_k D_s of the tile's run
-  double nbar[SMAX][kWave];             // mean occupancy of item (lane, s)
-  int npost[SMAX][kWave];               // post-reaction count of item (lane, s)
-  uint16_t item[SMAX * kWave];          // packed items: lane << 4 | species
+  double nbar[kWave];                   // mean occupancy of the round's items
+  int npost[kWave];                     // post-reaction count of the round's items
+  uint16_t item[kWave];                 // the round's items: lane << 4 | species
   int4 nbr[kWave];
   double2 geo[2][kWave];                // (G, cum0), (cum1, cum2)
   int tet[kWave];
@@ -816,8 +816,9 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
 // from the packed (uniform) reaction entry; values below 2^-1000 are taken as
 // zero.
 template <int SMAX, int RMAX, typename NV>
-__device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const double (&c)[RMAX], const NV& N,
-                                                double (&a)[RMAX], unsigned long long which) {
+__device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const double* kreg, double nav,
+                                                double inv_nav, const NV& N, double (&a)[RMAX],
+                                                unsigned long long which) {
 #pragma unroll
   for (int r = 0; r < RMAX; ++r) {
     if (r >= R) {
@@ -826,6 +827,9 @@ __device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const 
       double v;
       const int info = A.info[r];
       const int order = info & 0xff;
+      // c_r = k N_A V, k or k / (N_A V) by reaction order
+      const double kr = kreg[r];
+      const double cr = order == 0 ? kr * nav : (order == 1 ? kr : kr * inv_nav);
       const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
       const int n0 = s0 < SMAX ? N[s0] : 0;
       const int n1 = s1 < SMAX ? N[s1] : 0;
@@ -834,7 +838,7 @@ __device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const 
       else if (order == 1) h = (double)n0;
       else if (s0 == s1) h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
       else h = (double)n0 * (double)n1;
-      v = c[r] * h;
+      v = cr * h;
       a[r] = v >= 0x1p-1000 ? v : 0.0;
     }
   }
@@ -913,24 +917,27 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
       wave_sync();
       const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(L.kc_w);
 
+      // the tet's neighbours and couplings wait in LDS while the SSA runs
+      L.tet[lane] = i;
+      L.nbr[lane] = nb;
+      L.geo[0][lane] = ga;
+      L.geo[1][lane] = gb;
+
       unsigned long long n_ev = 0, n_mv = 0;
       int errbits = 0;
       uint32_t mask = 0;
+      double nbv[SMAX];  // mean occupancies of the tet's items
+      int npv[SMAX];     // post-reaction counts
       if (active) {
         // counts as one vector value (uniform species indices select
-        // registers); c_r = k N_A V, k or k / (N_A V) by reaction order
+        // registers); rate constants of the tet's region from LDS
         int __attribute__((ext_vector_type(SMAX))) Nv;
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) Nv[s] = N[s];
         const double inv_nav = 1.0 / nav;
-        double c[RMAX], a[RMAX];
-#pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-          const int order = r < R ? (A.info[r] & 0xff) : 1;
-          const double kr = r < R ? s_kc[reg][r] : 0.0;
-          c[r] = order == 0 ? kr * nav : (order == 1 ? kr : kr * inv_nav);
-        }
-        propensities_of<SMAX, RMAX>(A, R, c, Nv, a, ~0ull);
+        const double* kreg = s_kc[reg];
+        double a[RMAX];
+        propensities_of<SMAX, RMAX>(A, R, kreg, nav, inv_nav, Nv, a, ~0ull);
 
         // ---- reaction SSA operator over [0, tau_k] ----
         double O[SMAX], tS[SMAX];
@@ -973,7 +980,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
               }
             }
           }
-          propensities_of<SMAX, RMAX>(A, R, c, Nv, a, dep);
+          propensities_of<SMAX, RMAX>(A, R, kreg, nav, inv_nav, Nv, a, dep);
           ++ev_tet;
           if (errbits) break;
           if (ev_tet >= (unsigned int)kEventCap) {
@@ -984,48 +991,68 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
         n_ev = ev_tet;
 
         // ---- mean occupancies; items for the diffusion operator ----
-        L.tet[lane] = i;
-        L.nbr[lane] = nb;
-        L.geo[0][lane] = ga;
-        L.geo[1][lane] = gb;
+        const bool coupled = L.geo[0][lane].x > 0.0;
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
+          nbv[s] = 0.0;
+          npv[s] = 0;
           if (s >= S) continue;
           const int n = Nv[s];
           const double occ = (O[s] + (double)n * (tau - tS[s])) / tau;
           const double nbar = ((touched >> s) & 1u) ? occ : (double)n;
-          if (((dmask >> s) & 1u) && ga.x > 0.0 && nbar > 0.0) {
+          if (((dmask >> s) & 1u) && coupled && nbar > 0.0) {
             mask |= 1u << s;
-            L.nbar[s][lane] = nbar;
-            L.npost[s][lane] = n;
+            nbv[s] = nbar;
+            npv[s] = n;
           } else if (n != 0) {
             atomicAdd(cc.cout + (size_t)s * T + i, n);  // nothing can leave
           }
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          nbv[s] = 0.0;
+          npv[s] = 0;
         }
       }
       const int cnt = __popc(mask);
       const int incl = wave_inclusive_scan(cnt);
       const int total = __shfl(incl, kWave - 1);
-      int pos = incl - cnt;
+      const int first = incl - cnt;
+      // items in rounds of 64: each lane parks the items of the round that
+      // are its own, then every lane samples one
+      for (int r0 = 0; r0 < total; r0 += kWave) {
+        int pos = first;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if ((mask >> s) & 1u) L.item[pos++] = (uint16_t)((lane << 4) | s);
-      wave_sync();
-      for (int j = lane; j < total; j += kWave) {
-        const int it = L.item[j];
-        const int Ln = it >> 4, sp = it & 15;
-        const int ti = L.tet[Ln];
-        const int npost = L.npost[sp][Ln];
-        const int4 tnb = L.nbr[Ln];
-        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[sp][Ln], npost,
-                                         tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
-        int32_t* out_s = cc.cout + (size_t)sp * T;
-        if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
-        if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
-        if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
-        if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
-        if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
-        n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+        for (int s = 0; s < SMAX; ++s) {
+          if ((mask >> s) & 1u) {
+            const unsigned slot = (unsigned)(pos - r0);
+            if (slot < (unsigned)kWave) {
+              L.item[slot] = (uint16_t)((lane << 4) | s);
+              L.nbar[slot] = nbv[s];
+              L.npost[slot] = npv[s];
+            }
+            ++pos;
+          }
+        }
+        wave_sync();
+        if (lane < total - r0) {
+          const int it = L.item[lane];
+          const int Ln = it >> 4, sp = it & 15;
+          const int ti = L.tet[Ln];
+          const int npost = L.npost[lane];
+          const int4 tnb = L.nbr[Ln];
+          const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[lane], npost,
+                                           tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
+          int32_t* out_s = cc.cout + (size_t)sp * T;
+          if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
+          if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
+          if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
+          if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
+          if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
+          n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+        }
+        wave_sync();  // the round's LDS entries are rebuilt for the next
       }
       const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv);
       if (lane == 0) {
@@ -1038,8 +1065,12 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
   }
 }
 
+// Three waves per SIMD: the diffusion blocks need the occupancy to hide
+// their load latency, so the compiler keeps the event part (the larger
+// register footprint) within that budget, spilling if it must.
 template <int SMAX, int RMAX>
-__global__ void __launch_bounds__(kWave) window_main_kernel(const StepArgs A) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
+window_main_kernel(const StepArgs A) {
   __shared__ MainLds<SMAX> lds;
   const int k = step_index(A);
   const int n_queued = __builtin_amdgcn_readfirstlane(A.evq_count[k & 1]);
