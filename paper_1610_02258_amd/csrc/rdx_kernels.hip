@@ -221,36 +221,58 @@ __device__ __forceinline__ double mass_action(int info, double k, int n0, int n1
   return a >= 0x1p-1000 ? a : 0.0;
 }
 
+// The same a_r in a branch-free form whose products are those of the
+// case-by-case definition: h = (x y) w with x = N_A (1 for order 0), y = N_B,
+// N_A - 1 (A + A) or 1, w = 1/2 for A + A, and c = k f with f = N_A V, 1 or
+// 1 / (N_A V).  `N` holds the counts as one vector value, so that the uniform
+// species index selects a register.
+template <int SMAX, typename NV>
+__device__ __forceinline__ double propensity(int info, double k, const NV& N, double nav, double inv_nav) {
+  const int order = info & 0xff;
+  const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
+  const bool same = order == 2 && s0 == s1;
+  const int x = order == 0 ? 1 : (s0 < SMAX ? N[s0] : 0);
+  const int y = order == 2 ? (s1 < SMAX ? N[s1] : 0) - (same ? 1 : 0) : 1;
+  const double f = order == 0 ? nav : (order == 1 ? 1.0 : inv_nav);
+  const double v = (k * f) * (((double)x * (double)y) * (same ? 0.5 : 1.0));
+  return v >= 0x1p-1000 ? v : 0.0;
+}
+
 // Composition: groups of reactions with equal binary exponent, visited from
 // the largest exponent down, picked with probability proportional to their
 // totals; rejection: a uniform member is accepted with probability a / 2^g.
-// The exponent fields are taken once (absent reactions as -1); group totals
-// are summed in reaction order.
-template <int RMAX>
-__device__ int cr_select(const double (&a)[RMAX], int R, double a0, Draw53& st) {
-  int E[RMAX];
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) E[r] = (r < R && a[r] > 0.0) ? exp_field(a[r]) : -1;
+// Group totals are summed in reaction order.  The propensities are the
+// lane's column of an LDS table (a_r at col[r * stride]); the scans are
+// loops, so that one SSA step stays a short stretch of code.
+__device__ int cr_select_col(const double* col, int stride, int R, double a0, Draw53& st) {
   double x = st.co() * a0;
   int gprev = 4096, chosen = -1;
   for (;;) {
     int gcur = -1;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (E[r] < gprev && E[r] > gcur) gcur = E[r];
+#pragma unroll 4
+    for (int r = 0; r < R; ++r) {
+      const double v = col[r * stride];
+      const int e = v > 0.0 ? exp_field(v) : -1;
+      if (e < gprev && e > gcur) gcur = e;
+    }
     if (gcur < 0) break;
     double sum = 0.0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (E[r] == gcur) sum = sum + a[r];
+#pragma unroll 4
+    for (int r = 0; r < R; ++r) {
+      const double v = col[r * stride];
+      if (v > 0.0 && exp_field(v) == gcur) sum = sum + v;
+    }
     chosen = gcur;
     if (x < sum) break;
     x = x - sum;
     gprev = gcur;
   }
   int n = 0;
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) n += E[r] == chosen;
+#pragma unroll 4
+  for (int r = 0; r < R; ++r) {
+    const double v = col[r * stride];
+    n += (v > 0.0 && exp_field(v) == chosen) ? 1 : 0;
+  }
   const double bound = __longlong_as_double((long long)(chosen + 1) << 52);
   for (;;) {
     const double u2 = st.co();
@@ -259,15 +281,17 @@ __device__ int cr_select(const double (&a)[RMAX], int R, double a0, Draw53& st) 
     const double u3 = st.co();
     double aj = 0.0;
     int rj = 0, seen = 0;
-#pragma unroll
-    for (int r = 0; r < RMAX; ++r)
-      if (E[r] == chosen) {
+#pragma unroll 4
+    for (int r = 0; r < R; ++r) {
+      const double v = col[r * stride];
+      if (v > 0.0 && exp_field(v) == chosen) {
         if (seen == j) {
-          aj = a[r];
+          aj = v;
           rj = r;
         }
         ++seen;
       }
+    }
     if (u3 * bound < aj) return rj;
   }
 }
@@ -645,13 +669,22 @@ struct DiffusionLds {
   double2 geo[2][kWave];        // (G, cum0), (cum1, cum2)
 };
 
-template <int SMAX>
+// Lanes of an event chunk: the propensity table takes RMAX doubles per lane,
+// kept to 6 KiB.
+template <int RMAX>
+constexpr int chunk_width() {
+  return RMAX * 8 * kWave <= 6144 ? kWave : (RMAX * 8 * 32 <= 6144 ? 32 : 16);
+}
+
+template <int SMAX, int RMAX>
 struct EventLds {
+  static constexpr int CW = chunk_width<RMAX>();
   // net changes and dependencies (copied whole from the device model) and
   // the rate constants of the tile's run by region
   uint32_t delta_w[32 * 16 / 4];        // int8 [32][16]
   uint32_t deps_w[32 * 2];              // uint64 [32]: reactions whose propensity a reaction changes
   uint32_t kc_w[kMaxRegions * 32 * 2];  // double [8][32]
+  double a[RMAX][CW];                   // propensities of the chunk's tets, one column per lane
   double td[SMAX];                      // tau_k D_s of the tile's run
   double nbar[kWave];                   // mean occupancy of the round's items
   int npost[kWave];                     // post-reaction count of the round's items
@@ -661,10 +694,10 @@ struct EventLds {
   int tet[kWave];
 };
 
-template <int SMAX>
+template <int SMAX, int RMAX>
 union MainLds {
   DiffusionLds<SMAX> d;
-  EventLds<SMAX> e;
+  EventLds<SMAX, RMAX> e;
 };
 
 // Diffusion blocks (b of G): the tets not listed, tile by tile, persistent,
@@ -812,42 +845,12 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
 }
 
-// a_r = c_r h_r(N) for the reactions in `which`, h by the reaction's order
-// from the packed (uniform) reaction entry; values below 2^-1000 are taken as
-// zero.
-template <int SMAX, int RMAX, typename NV>
-__device__ __forceinline__ void propensities_of(const StepArgs& A, int R, const double* kreg, double nav,
-                                                double inv_nav, const NV& N, double (&a)[RMAX],
-                                                unsigned long long which) {
-#pragma unroll
-  for (int r = 0; r < RMAX; ++r) {
-    if (r >= R) {
-      a[r] = 0.0;
-    } else if ((which >> r) & 1ull) {
-      double v;
-      const int info = A.info[r];
-      const int order = info & 0xff;
-      // c_r = k N_A V, k or k / (N_A V) by reaction order
-      const double kr = kreg[r];
-      const double cr = order == 0 ? kr * nav : (order == 1 ? kr : kr * inv_nav);
-      const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-      const int n0 = s0 < SMAX ? N[s0] : 0;
-      const int n1 = s1 < SMAX ? N[s1] : 0;
-      double h;
-      if (order == 0) h = 1.0;
-      else if (order == 1) h = (double)n0;
-      else if (s0 == s1) h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
-      else h = (double)n0 * (double)n1;
-      v = cr * h;
-      a[r] = v >= 0x1p-1000 ? v : 0.0;
-    }
-  }
-}
-
 // Event blocks (b of E): the queued tiles b, b + E, ...; a tile's listed
-// tets (one run) one per lane.
+// tets (one run) one per lane, CW at a time.
 template <int SMAX, int RMAX>
-__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued, EventLds<SMAX>& L) {
+__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued,
+                                           EventLds<SMAX, RMAX>& L) {
+  constexpr int CW = EventLds<SMAX, RMAX>::CW;
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
   bool tables = false;
@@ -855,9 +858,10 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
   uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
 
   for (int q = b; q < n_queued; q += E) {
-    {
-      const int tile = A.evq[q];
-      const int n_work = A.wl_tile_count[tile];
+    const int tile = A.evq[q];
+    const int n_tile = A.wl_tile_count[tile];
+    for (int c0 = 0; c0 < n_tile; c0 += CW) {
+      const int n_work = n_tile - c0 < CW ? n_tile - c0 : CW;
       const TileCtx cc = tile_ctx(A, tile, k);
       const cptr<RunDesc> rd = cc.rd;
       const int T = cc.T;
@@ -865,7 +869,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
 
       // the entry holds everything the tet needs: one round of loads
       const bool active = lane < n_work;
-      const size_t e = (size_t)tile * kWave + lane;
+      const size_t e = (size_t)tile * kWave + (size_t)(c0 + lane);
       int N[SMAX];
       int i = 0;
       double nav = 1.0;
@@ -936,8 +940,9 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
         for (int s = 0; s < SMAX; ++s) Nv[s] = N[s];
         const double inv_nav = 1.0 / nav;
         const double* kreg = s_kc[reg];
-        double a[RMAX];
-        propensities_of<SMAX, RMAX>(A, R, kreg, nav, inv_nav, Nv, a, ~0ull);
+        double* col = &L.a[0][lane];  // a_r at col[r * CW]
+#pragma unroll 1
+        for (int r = 0; r < R; ++r) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
 
         // ---- reaction SSA operator over [0, tau_k] ----
         double O[SMAX], tS[SMAX];
@@ -952,14 +957,13 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
         unsigned int ev_tet = 0;
         for (;;) {
           double a0 = 0.0;
-#pragma unroll
-          for (int r = 0; r < RMAX; ++r)
-            if (r < R) a0 = a0 + a[r];
+#pragma unroll 4
+          for (int r = 0; r < R; ++r) a0 = a0 + col[r * CW];
           if (!(a0 > 0.0)) break;
           const double u = st.oc();
           const double t_reac = -ln_basic(u) / a0;
           if (dt + t_reac > tau) break;
-          const int rn = cr_select<RMAX>(a, R, a0, st);
+          const int rn = cr_select_col(col, CW, R, a0, st);
           dt = dt + t_reac;
           // few lanes of a wave are in the loop at a time, so branches that
           // skip unchanged species and unaffected reactions are cheap
@@ -980,7 +984,10 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
               }
             }
           }
-          propensities_of<SMAX, RMAX>(A, R, kreg, nav, inv_nav, Nv, a, dep);
+          // the propensities that read a changed species
+#pragma unroll 1
+          for (int r = 0; r < R; ++r)
+            if ((dep >> r) & 1ull) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
           ++ev_tet;
           if (errbits) break;
           if (ev_tet >= (unsigned int)kEventCap) {
@@ -1071,7 +1078,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 window_main_kernel(const StepArgs A) {
-  __shared__ MainLds<SMAX> lds;
+  __shared__ MainLds<SMAX, RMAX> lds;
   const int k = step_index(A);
   const int n_queued = __builtin_amdgcn_readfirstlane(A.evq_count[k & 1]);
   if (blockIdx.x == 0 && threadIdx.x == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
