@@ -96,6 +96,36 @@ size_t DeviceArena::largest_free() const {
 }
 
 // ------------------------------------------------------------------ model ----
+void listing_pairs(const DevModel& m, int32_t pairs[32], int32_t* n_pairs, int32_t pair_of[32]) {
+  int n = 0;
+  for (int r = 0; r < 32; ++r) pair_of[r] = -1;
+  for (int r = 0; r < m.R; ++r) {
+    const int info = m.info[r];
+    if ((info & 0xff) != 2) continue;
+    const int a = (info >> 8) & 0xff, b = (info >> 16) & 0xff;
+    const int key = a | (b << 8) | ((a == b ? 1 : 0) << 16);
+    int p = 0;
+    while (p < n && pairs[p] != key) ++p;
+    if (p == n) pairs[n++] = key;
+    pair_of[r] = p;
+  }
+  for (int p = n; p < 32; ++p) pairs[p] = 0;
+  *n_pairs = n;
+}
+
+void listing_coefficients(const DevModel& m, const double* k, double* out) {
+  int32_t pairs[32], pair_of[32], n_pairs = 0;
+  listing_pairs(m, pairs, &n_pairs, pair_of);
+  for (int j = 0; j < kLStride; ++j) out[j] = 0.0;
+  for (int r = 0; r < m.R; ++r) {
+    const int info = m.info[r];
+    const int order = info & 0xff, a = (info >> 8) & 0xff, b = (info >> 16) & 0xff;
+    if (order == 0) out[0] += k[r];
+    else if (order == 1) out[1 + a] += k[r];
+    else out[17 + pair_of[r]] += a == b ? 0.5 * k[r] : k[r];
+  }
+}
+
 DevModel make_dev_model(const HostInstance& I) {
   DevModel m;
   std::memset(&m, 0, sizeof m);
@@ -133,7 +163,7 @@ size_t Engine::run_bytes(const HostInstance& I) {
   const size_t T = (size_t)I.T, S = (size_t)I.S;
   size_t b = 2 * align_up(4 * S * T) + align_up(16 * T) + align_up(32 * T) + align_up(8 * T);
   if (I.n_regions > 1) b += align_up(T);
-  b += align_up(sizeof(double) * kMaxRegions * 32);  // rate constants
+  b += align_up(sizeof(double) * kMaxRegions * (32 + kLStride));  // rate constants, listing coefficients
   b += align_up(sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t));  // tallies, error flag
   return b;
 }
@@ -242,7 +272,8 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
   r->geo = reinterpret_cast<double*>(carve(32 * T));
   r->nav = reinterpret_cast<double*>(carve(8 * T));
   r->region = I.n_regions > 1 ? reinterpret_cast<uint8_t*>(carve(T)) : nullptr;
-  r->kcst = reinterpret_cast<double*>(carve(sizeof(double) * kMaxRegions * 32));
+  r->kcst = reinterpret_cast<double*>(carve(sizeof(double) * kMaxRegions * (32 + kLStride)));
+  r->lcoef = r->kcst + kMaxRegions * 32;
   const size_t misc_bytes = sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t);
   char* misc = carve(misc_bytes);
   r->tally = reinterpret_cast<unsigned long long*>(misc);
@@ -257,9 +288,11 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
     geo[4 * i + 2] = I.cum[4 * i + 1];
     geo[4 * i + 3] = I.cum[4 * i + 2];
   }
-  std::vector<double> kc((size_t)kMaxRegions * 32, 0.0);
-  for (int reg = 0; reg < I.n_regions; ++reg)
+  std::vector<double> kc((size_t)kMaxRegions * (32 + kLStride), 0.0);
+  for (int reg = 0; reg < I.n_regions; ++reg) {
     for (int q = 0; q < I.R; ++q) kc[(size_t)reg * 32 + q] = I.kcst[(size_t)reg * I.R + q];
+    listing_coefficients(model_host_, &I.kcst[(size_t)reg * I.R], &kc[(size_t)kMaxRegions * 32 + (size_t)reg * kLStride]);
+  }
   hipError_t e = hipMemcpyAsync(r->nbr, I.nbr.data(), 16 * T, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->geo, geo.data(), 32 * T, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->nav, I.nav.data(), 8 * T, hipMemcpyHostToDevice, stream);
@@ -401,6 +434,7 @@ rdx_status Engine::upload_tables(const std::vector<Run*>& active, int64_t k0, hi
     d.nav = r->nav;
     d.region = r->region;
     d.kcst = r->kcst;
+    d.lcoef = r->lcoef;
     d.tally = r->tally;
     d.err = r->err;
     d.T = I.T;
@@ -531,6 +565,10 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.wl_stride = (int32_t)(64 * max_tiles_);
   a.model = model_;
   std::memcpy(a.info, model_host_.info, sizeof a.info);
+  {
+    int32_t pair_of[32];
+    listing_pairs(model_host_, a.pairs, &a.n_pairs, pair_of);
+  }
   a.wl_tile_count = wl_tile_count_;
   a.evq = evq_;
   a.evq_count = evq_count_;

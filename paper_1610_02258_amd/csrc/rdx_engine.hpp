@@ -62,7 +62,8 @@ struct Run {
   double* geo = nullptr;      // (G, cum0, cum1, cum2) per tet
   double* nav = nullptr;
   uint8_t* region = nullptr;  // only with more than one region
-  double* kcst = nullptr;     // [8][32]
+  double* kcst = nullptr;     // [8][32], then the listing coefficients
+  double* lcoef = nullptr;    // [8][kLStride]
   unsigned long long* tally = nullptr;  // [kTallySlots][2]
   int32_t* err = nullptr;
   double t = 0.0;

@@ -196,36 +196,14 @@ __device__ __forceinline__ int exp_field(double a) {
   return (int)((__double_as_longlong(a) >> 52) & 0x7ff);
 }
 
-// a_r = c_r h_r(N): c = k N_A V[L] (order 0), k (order 1), k / (N_A V[L])
-// (order 2); h = 1, N_A, N_A N_B or N_A (N_A - 1) / 2.  Values below 2^-1000
-// are taken as zero.  `info` is the packed reaction entry (uniform).
-__device__ __forceinline__ double mass_action(int info, double k, int n0, int n1, double nav,
-                                              double inv_nav) {
-  const int order = info & 0xff;
-  double c, h;
-  if (order == 0) {
-    c = k * nav;
-    h = 1.0;
-  } else if (order == 1) {
-    c = k;
-    h = (double)n0;
-  } else {
-    c = k * inv_nav;
-    if (((info >> 8) & 0xff) == ((info >> 16) & 0xff)) {
-      h = n0 >= 2 ? ((double)n0 * (double)(n0 - 1)) * 0.5 : 0.0;
-    } else {
-      h = (double)n0 * (double)n1;
-    }
-  }
-  const double a = c * h;
-  return a >= 0x1p-1000 ? a : 0.0;
-}
-
-// The same a_r in a branch-free form whose products are those of the
-// case-by-case definition: h = (x y) w with x = N_A (1 for order 0), y = N_B,
-// N_A - 1 (A + A) or 1, w = 1/2 for A + A, and c = k f with f = N_A V, 1 or
-// 1 / (N_A V).  `N` holds the counts as one vector value, so that the uniform
-// species index selects a register.
+// a_r = c_r h_r(N) with c = k N_A V[L] (order 0), k (order 1), k / (N_A V[L])
+// (order 2) and h = 1, N_A, N_A N_B or N_A (N_A - 1) / 2, in a branch-free
+// form whose products are those of the case-by-case definition: h = (x y) w
+// with x = N_A (1 for order 0), y = N_B, N_A - 1 (A + A) or 1, w = 1/2 for
+// A + A, and c = k f with f = N_A V, 1 or 1 / (N_A V).  Values below 2^-1000
+// are taken as zero.  `info` is the packed reaction entry (uniform); `N`
+// holds the counts as one vector value, so that the uniform species index
+// selects a register.
 template <int SMAX, typename NV>
 __device__ __forceinline__ double propensity(int info, double k, const NV& N, double nav, double inv_nav) {
   const int order = info & 0xff;
@@ -554,19 +532,39 @@ __device__ __forceinline__ void load_counts(const TileCtx& c, int S, int i, TetC
 // Persistent: each block walks its tiles, the next tile's loads in flight
 // while the current one is worked on.  Values that depend only on the run
 // (rate constants, the key) are fetched once per run change.
+// a_0 of one tet from the regrouped listing coefficients of its region (`lc`,
+// a scalar pointer when the run has one region, a per-lane one otherwise).
+// The terms are those of the reaction-by-reaction sum, so the result agrees
+// with it to within a few roundings (relative 1e-14 at most); it is only used
+// with a margin far above that.
+template <int SMAX, typename P, typename NV>
+__device__ __forceinline__ double listing_rate(const StepArgs& A, int S, P lc, const NV& N, double nav,
+                                               double inv_nav) {
+  double lin = nav * lc[0];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s)
+    if (s < S) lin = lin + lc[1 + s] * (double)N[s];
+  double quad = 0.0;
+#pragma unroll 1
+  for (int p = 0; p < A.n_pairs; ++p) {
+    const int pr = A.pairs[p];
+    const int a = pr & 0xff, b = (pr >> 8) & 0xff;
+    const int x = a < SMAX ? N[a] : 0;
+    const int y = (b < SMAX ? N[b] : 0) - ((pr >> 16) & 1);
+    quad = quad + lc[17 + p] * ((double)x * (double)y);
+  }
+  return lin + inv_nav * quad;
+}
+
+// Persistent: each block walks its tiles, the next tile's loads in flight
+// while the current one is worked on.
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) {
-  __shared__ double s_kc[kMaxRegions][RMAX];  // rate constants of the current run by region
-  __shared__ int s_info[RMAX];                // packed reaction entries
-
   const int lane = threadIdx.x;
-  const int S = A.S, R = A.R;
+  const int S = A.S;
   const int k = step_index(A);
   const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(blockIdx.x, gridDim.x, n_tiles);
-  int cache_run = -1;
-  uint32_t key0 = 0, key1 = 0;
-  if (lane < RMAX) s_info[lane] = lane < R ? A.model->info[lane] : 0;
 
   TileCtx cc, nc;
   TetCounts<SMAX> cur, nxt;
@@ -582,35 +580,16 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     const cptr<RunDesc> rd = cc.rd;
     const int i = cc.base + lane;
     const bool active = i < cc.T;
-    if (run_active && cc.run != cache_run) {
-      key0 = rd->key0;
-      key1 = rd->key1;
-      const cptr<double> kc = as_const(rd->kcst);
-      const int nreg = rd->region != nullptr ? kMaxRegions : 1;
-      for (int x = lane; x < nreg * RMAX; x += kWave) s_kc[x / RMAX][x % RMAX] = kc[(x / RMAX) * 32 + (x % RMAX)];
-      cache_run = cc.run;
-      wave_sync();
-    }
 
-    // propensities a_r = c_r h_r(N), summed in reaction order
+    // a_0 from the listing coefficients
     const double nav = cur.nav;
     const int reg = cur.reg;
     const auto Nc = cur.N;
     double a0 = 0.0;
     if (run_active) {
-      // a loop over the reactions (not unrolled): the packed entry is an LDS
-      // broadcast made uniform, its species are uniform register indices,
-      // the rate constant an LDS broadcast (or per region)
       const double inv_nav = 1.0 / nav;
-#pragma unroll 1
-      for (int r = 0; r < R; ++r) {
-        const int info = __builtin_amdgcn_readfirstlane(s_info[r]);
-        const double kr = s_kc[reg][r];
-        const int s0 = (info >> 8) & 0xff, s1 = (info >> 16) & 0xff;
-        const int n0 = s0 < SMAX ? Nc[s0] : 0;
-        const int n1 = s1 < SMAX ? Nc[s1] : 0;
-        a0 = a0 + mass_action(info, kr, n0, n1, nav, inv_nav);
-      }
+      if (rd->region == nullptr) a0 = listing_rate<SMAX>(A, S, as_const(rd->lcoef), Nc, nav, inv_nav);
+      else a0 = listing_rate<SMAX>(A, S, rd->lcoef + reg * kLStride, Nc, nav, inv_nav);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (has_next) {
@@ -619,18 +598,18 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // first waiting time: does an event fall inside the window?  Since
-    // -ln(u) >= 1 - u, a draw with 1 - u above a0 tau (with a 1e-7 relative
-    // margin, far above the rounding of ln and of the division) certainly
-    // gives t_reac > tau; only the other draws evaluate t_reac = -ln(u)/a0.
+    // listing: the window's first SSA event falls inside [0, tau_k] only if
+    // t_reac = -ln(u) / a0 <= tau_k, and -ln(u) >= 1 - u; so a tet whose first
+    // uniform u of the window has 1 - u above a0 tau_k (with a relative
+    // margin of 1e-6, far above the rounding of a0, of ln and of the
+    // division) has no event, and every other tet with a0 > 0 is listed.  A
+    // listed tet without an event is harmless: its SSA ends at the first draw
+    // and its items are those of an unlisted tet.
     bool event = false;
     if (run_active && active && a0 > 0.0) {
-      Draw53 st(key0, key1, 0u, (uint32_t)i, cc.window);
+      Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
       const double u = st.oc();
-      if (!(1.0 - u > (cc.tau_k * a0) * 1.0000001)) {
-        const double t_reac = -ln_basic(u) / a0;
-        event = !(0.0 + t_reac > cc.tau_k);
-      }
+      event = !(1.0 - u > (cc.tau_k * a0) * 1.000001);
     }
     const unsigned long long ballot = __ballot(event);
     if (lane == 0) {

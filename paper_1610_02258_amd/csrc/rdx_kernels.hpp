@@ -25,6 +25,16 @@ struct alignas(16) DevModel {
   unsigned long long deps[32];
 };
 
+// Listing coefficients of one region: a_0 regrouped as
+//   N_A V alpha + sum_s beta_s N_s + (1 / N_A V) sum_p gamma_p x_p y_p
+// with alpha the summed order-0 constants, beta_s the summed order-1
+// constants of species s, and gamma_p the summed order-2 constants of
+// reactant pair p (x y = N_a N_b, or N_a (N_a - 1) with the 1/2 folded into
+// gamma_p for A + A).
+constexpr int kLStride = 56;  // 1 + 16 + 32, rounded up
+void listing_pairs(const DevModel& m, int32_t pairs[32], int32_t* n_pairs, int32_t pair_of[32]);
+void listing_coefficients(const DevModel& m, const double* k, double* out);  // one region: k[R] -> out[kLStride]
+
 // One run of the batch, as the kernels read it (device memory).
 struct alignas(16) RunDesc {
   int32_t* cnt[2];             // [S][T] count buffers; window w reads cnt[w & 1], writes cnt[(w + 1) & 1]
@@ -33,6 +43,7 @@ struct alignas(16) RunDesc {
   const double* nav;           // [T] N_A V[L]
   const uint8_t* region;       // [T] region labels, nullptr when the model has one region
   const double* kcst;          // [8][32] rate constants by region
+  const double* lcoef;         // [8][kLStride] listing coefficients by region (alpha, beta[16], gamma[32])
   unsigned long long* tally;   // [kTallySlots][2] SSA events, molecules moved (summed on read)
   int32_t* err;                // error-flag bits
   int32_t T;
@@ -58,6 +69,8 @@ struct StepArgs {
   int32_t wl_stride;           // worklist capacity, 64 entries per tile (row stride of wl_cnt)
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
+  int32_t n_pairs;             // distinct reactant pairs of the second-order reactions
+  int32_t pairs[32];           // a | b << 8 | (a == b) << 16
   // worklist of the tets whose first SSA event falls inside the window: the
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
   unsigned long long* wl_mask; // [tiles] listed tets of each tile (bit = lane)
