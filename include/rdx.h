@@ -183,7 +183,7 @@ rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
  *   autotune       1: time the candidate shapes on the next windows run
  *                  (those windows are real work of the simulation) and keep
  *                  the fastest; get returns 1 while tuning is under way
- *   fast_grid_div  all-tets kernel grid = resident grid / this (1, 2 or 4)
+ *   fast_grid_div  main kernel grid = resident grid / this (1, 2 or 4)
  *   graph_windows  windows per captured HIP graph, replayed as one launch;
  *                  1 = plain launches (1..256) */
 typedef struct rdx_exec_options {
