@@ -535,15 +535,14 @@ __device__ __forceinline__ void load_counts(const TileCtx& c, int S, int i, TetC
 // a_0 of one tet from the regrouped listing coefficients of its region (`lc`,
 // a scalar pointer when the run has one region, a per-lane one otherwise).
 // The terms are those of the reaction-by-reaction sum, so the result agrees
-// with it to within a few roundings (relative 1e-14 at most); it is only used
-// with a margin far above that.
+// with it to within a few roundings (relative 1e-14 at most; fused
+// multiply-adds are fine here); it is only used with a margin far above that.
 template <int SMAX, typename P, typename NV>
-__device__ __forceinline__ double listing_rate(const StepArgs& A, int S, P lc, const NV& N, double nav,
-                                               double inv_nav) {
+__device__ __forceinline__ double listing_rate(const StepArgs& A, P lc, const NV& N, double nav, double inv_nav) {
+  // beta_s is zero for s >= S, and so are the counts there
   double lin = nav * lc[0];
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s)
-    if (s < S) lin = lin + lc[1 + s] * (double)N[s];
+  for (int s = 0; s < SMAX; ++s) lin = __builtin_fma(lc[1 + s], (double)N[s], lin);
   double quad = 0.0;
 #pragma unroll 1
   for (int p = 0; p < A.n_pairs; ++p) {
@@ -551,9 +550,9 @@ __device__ __forceinline__ double listing_rate(const StepArgs& A, int S, P lc, c
     const int a = pr & 0xff, b = (pr >> 8) & 0xff;
     const int x = a < SMAX ? N[a] : 0;
     const int y = (b < SMAX ? N[b] : 0) - ((pr >> 16) & 1);
-    quad = quad + lc[17 + p] * ((double)x * (double)y);
+    quad = __builtin_fma(lc[17 + p], (double)x * (double)y, quad);
   }
-  return lin + inv_nav * quad;
+  return __builtin_fma(inv_nav, quad, lin);
 }
 
 // Persistent: each block walks its tiles, the next tile's loads in flight
@@ -588,8 +587,8 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     double a0 = 0.0;
     if (run_active) {
       const double inv_nav = 1.0 / nav;
-      if (rd->region == nullptr) a0 = listing_rate<SMAX>(A, S, as_const(rd->lcoef), Nc, nav, inv_nav);
-      else a0 = listing_rate<SMAX>(A, S, rd->lcoef + reg * kLStride, Nc, nav, inv_nav);
+      if (rd->region == nullptr) a0 = listing_rate<SMAX>(A, as_const(rd->lcoef), Nc, nav, inv_nav);
+      else a0 = listing_rate<SMAX>(A, rd->lcoef + reg * kLStride, Nc, nav, inv_nav);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (has_next) {

@@ -135,6 +135,27 @@ def test_random_models_parity(rdx, oracle_lib, case):
     _assert_same(sim, ref, "3 more windows")
 
 
+@pytest.mark.parametrize("S,R", [(16, 20), (16, 30), (12, 12)])
+def test_dense_events_every_tet_listed(rdx, oracle_lib, S, R):
+    """Random models with a dozen molecules per species and tet: nearly every
+    tet has SSA events in every window, so tiles list up to 64 tets, which the
+    event blocks take in chunks of 64, 32 or 16 lanes by reaction-table size;
+    2 regions, ragged last tile."""
+    rng = np.random.default_rng(50 + S + R)
+    mesh = I.box_mesh(6, 5, 4, 0.5e-6, jitter=0.1, seed=S + R)  # 720 tets: 11 full tiles + 16
+    mesh.region = rng.integers(0, 2, mesh.n_tets).astype(np.uint8)
+    md = random_model(rng, S, R, 2)
+    counts = random_counts(rng, S, mesh.n_tets, mean=12.0)
+    _say(f"case: dense events T={mesh.n_tets} S={S} R={R}")
+    sim, ref = _pair(rdx, oracle_lib, mesh.as_dict(), md, 900 + R, counts)
+    for k in range(3):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
+    # most tets had events (each listed tet is one lane of an event chunk)
+    assert ref.tallies.ssa_events > 3 * mesh.n_tets
+
+
 def test_edge_cases(rdx, oracle_lib):
     # all counts zero
     w = I.config_small()
