@@ -237,7 +237,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
-  RDX_HIP(hipMemset(evq_count_, 0, 2 * sizeof(int32_t)));
+  RDX_HIP(hipMemset(evq_count_, 0, 2 * sizeof(unsigned long long)));
   RDX_HIP(hipDeviceSynchronize());
   return RDX_OK;
 }

@@ -174,7 +174,7 @@ class Engine {
   int32_t* wl_tile_count_ = nullptr;
   unsigned long long* wl_mask_ = nullptr;
   int32_t* evq_ = nullptr;
-  int32_t* evq_count_ = nullptr;
+  unsigned long long* evq_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
   uint8_t* wl_reg_ = nullptr;
   int32_t* wl_cnt_ = nullptr;

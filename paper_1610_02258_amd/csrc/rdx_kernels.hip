@@ -615,7 +615,11 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
       A.wl_mask[tile] = ballot;
       if (ballot) {
         A.wl_tile_count[tile] = (int)__popcll(ballot);
-        A.evq[atomicAdd(A.evq_count + (k & 1), 1)] = tile;
+        // one atomic counts the queued tile (low word) and its listed tets
+        // (high word); the old low word is the tile's queue slot
+        const unsigned long long old =
+            atomicAdd(A.evq_count + (k & 1), ((unsigned long long)__popcll(ballot) << 32) | 1ull);
+        A.evq[(int)(old & 0xffffffffull)] = tile;
       }
     }
     if (event) {  // the tile's listed tets take its own worklist slots
@@ -823,229 +827,286 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
 }
 
-// Event blocks (b of E): the queued tiles b, b + E, ...; a tile's listed
-// tets (one run) one per lane, CW at a time.
+// One event chunk: up to CW listed tets of one run (worklist slot `slot` on
+// the lanes below `n_work`; `tile0` gives the run), one per lane: the SSA
+// window, the occupancies, then the diffusion of their items.  `tables`,
+// `cache_run` and `dmask` carry what is already in LDS from the previous
+// chunk of the block.
 template <int SMAX, int RMAX>
-__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued,
-                                           EventLds<SMAX, RMAX>& L) {
+__device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0, int n_work, size_t slot,
+                                            EventLds<SMAX, RMAX>& L, bool& tables, int& cache_run,
+                                            uint32_t& dmask) {
   constexpr int CW = EventLds<SMAX, RMAX>::CW;
   const int lane = threadIdx.x;
   const int S = A.S, R = A.R;
+  {
+    const TileCtx cc = tile_ctx(A, tile0, k);
+    const cptr<RunDesc> rd = cc.rd;
+    const int T = cc.T;
+    const double tau = cc.tau_k;
+
+    // the entry holds everything the tet needs: one round of loads
+    const bool active = lane < n_work;
+    const size_t e = slot;
+    int N[SMAX];
+    int i = 0;
+    double nav = 1.0;
+    int4 nb = make_int4(-1, -1, -1, -1);
+    double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+      N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
+    if (active) {
+      i = A.wl_tet[e];
+      nav = A.wl_nav[e];
+      nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
+      ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
+      gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
+    }
+    // tables and per-run constants: every load issued before any is used
+    const bool need_tables = !tables, need_run = cc.run != cache_run;
+    const bool regions = rd->region != nullptr;
+    const cptr<uint32_t> mw = as_const(reinterpret_cast<const uint32_t*>(A.model));
+    const cptr<uint32_t> kw = as_const(reinterpret_cast<const uint32_t*>(rd->kcst));
+    uint32_t d0 = 0, d1 = 0, dp = 0, kv[kMaxRegions];
+    double dv = 0.0;
+    int reg = 0;
+    if (need_tables) {
+      d0 = mw[offsetof(DevModel, delta) / 4 + lane];
+      d1 = mw[offsetof(DevModel, delta) / 4 + kWave + lane];
+      dp = mw[offsetof(DevModel, deps) / 4 + lane];
+    }
+    if (need_run) {
+#pragma unroll
+      for (int q = 0; q < kMaxRegions; ++q) kv[q] = (q == 0 || regions) ? kw[q * kWave + lane] : 0u;
+      if (lane < SMAX && lane < S) dv = rd->D[lane];
+    }
+    if (active && regions) reg = A.wl_reg[e];
+    if (need_tables) {
+      L.delta_w[lane] = d0;
+      L.delta_w[kWave + lane] = d1;
+      L.deps_w[lane] = dp;
+      tables = true;
+    }
+    if (need_run) {
+#pragma unroll
+      for (int q = 0; q < kMaxRegions; ++q)
+        if (q == 0 || regions) L.kc_w[q * kWave + lane] = kv[q];
+      if (lane < SMAX) L.td[lane] = lane < S ? tau * dv : 0.0;
+      dmask = (uint32_t)__ballot(lane < SMAX && lane < S && tau * dv > 0.0);
+      cache_run = cc.run;
+    }
+    wave_sync();
+    const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(L.kc_w);
+
+    // the tet's neighbours and couplings wait in LDS while the SSA runs
+    L.tet[lane] = i;
+    L.nbr[lane] = nb;
+    L.geo[0][lane] = ga;
+    L.geo[1][lane] = gb;
+
+    unsigned long long n_ev = 0, n_mv = 0;
+    int errbits = 0;
+    uint32_t mask = 0;
+    double nbv[SMAX];  // mean occupancies of the tet's items
+    int npv[SMAX];     // post-reaction counts
+    if (active) {
+      // counts as one vector value (uniform species indices select
+      // registers); rate constants of the tet's region from LDS
+      int __attribute__((ext_vector_type(SMAX))) Nv;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) Nv[s] = N[s];
+      const double inv_nav = 1.0 / nav;
+      const double* kreg = s_kc[reg];
+      double* col = &L.a[0][lane];  // a_r at col[r * CW]
+#pragma unroll 1
+      for (int r = 0; r < R; ++r) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
+
+      // ---- reaction SSA operator over [0, tau_k] ----
+      double O[SMAX], tS[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        O[s] = 0.0;
+        tS[s] = 0.0;
+      }
+      uint32_t touched = 0;
+      Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
+      double dt = 0.0;
+      unsigned int ev_tet = 0;
+      for (;;) {
+        double a0 = 0.0;
+#pragma unroll 4
+        for (int r = 0; r < R; ++r) a0 = a0 + col[r * CW];
+        if (!(a0 > 0.0)) break;
+        const double u = st.oc();
+        const double t_reac = -ln_basic(u) / a0;
+        if (dt + t_reac > tau) break;
+        const int rn = cr_select_col(col, CW, R, a0, st);
+        dt = dt + t_reac;
+        // few lanes of a wave are in the loop at a time, so branches that
+        // skip unchanged species and unaffected reactions are cheap
+        const uint4 drow = reinterpret_cast<const uint4*>(L.delta_w)[rn];
+        const unsigned long long dep = reinterpret_cast<const unsigned long long*>(L.deps_w)[rn];
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          if (s < S) {
+            const uint32_t wd = (s >> 2) == 0 ? drow.x : ((s >> 2) == 1 ? drow.y : ((s >> 2) == 2 ? drow.z : drow.w));
+            const int d = (int)(int8_t)((wd >> (8 * (s & 3))) & 0xffu);
+            if (d != 0) {
+              const int n = Nv[s];
+              O[s] = O[s] + (double)n * (dt - tS[s]);
+              tS[s] = dt;
+              touched |= 1u << s;
+              Nv[s] = n + d;
+              if (n + d > kCountCap) errbits |= kErrOverflow;
+            }
+          }
+        }
+        // the propensities that read a changed species
+#pragma unroll 1
+        for (int r = 0; r < R; ++r)
+          if ((dep >> r) & 1ull) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
+        ++ev_tet;
+        if (errbits) break;
+        if (ev_tet >= (unsigned int)kEventCap) {
+          errbits |= kErrEvents;
+          break;
+        }
+      }
+      n_ev = ev_tet;
+
+      // ---- mean occupancies; items for the diffusion operator ----
+      const bool coupled = L.geo[0][lane].x > 0.0;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        nbv[s] = 0.0;
+        npv[s] = 0;
+        if (s >= S) continue;
+        const int n = Nv[s];
+        const double occ = (O[s] + (double)n * (tau - tS[s])) / tau;
+        const double nbar = ((touched >> s) & 1u) ? occ : (double)n;
+        if (((dmask >> s) & 1u) && coupled && nbar > 0.0) {
+          mask |= 1u << s;
+          nbv[s] = nbar;
+          npv[s] = n;
+        } else if (n != 0) {
+          atomicAdd(cc.cout + (size_t)s * T + i, n);  // nothing can leave
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        nbv[s] = 0.0;
+        npv[s] = 0;
+      }
+    }
+    const int cnt = __popc(mask);
+    const int incl = wave_inclusive_scan(cnt);
+    const int total = __shfl(incl, kWave - 1);
+    const int first = incl - cnt;
+    // items in rounds of 64: each lane parks the items of the round that
+    // are its own, then every lane samples one
+    for (int r0 = 0; r0 < total; r0 += kWave) {
+      int pos = first;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) {
+        if ((mask >> s) & 1u) {
+          const unsigned slot = (unsigned)(pos - r0);
+          if (slot < (unsigned)kWave) {
+            L.item[slot] = (uint16_t)((lane << 4) | s);
+            L.nbar[slot] = nbv[s];
+            L.npost[slot] = npv[s];
+          }
+          ++pos;
+        }
+      }
+      wave_sync();
+      if (lane < total - r0) {
+        const int it = L.item[lane];
+        const int Ln = it >> 4, sp = it & 15;
+        const int ti = L.tet[Ln];
+        const int npost = L.npost[lane];
+        const int4 tnb = L.nbr[Ln];
+        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[lane], npost,
+                                         tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
+        int32_t* out_s = cc.cout + (size_t)sp * T;
+        if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
+        if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
+        if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
+        if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
+        if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
+        n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+      }
+      wave_sync();  // the round's LDS entries are rebuilt for the next
+    }
+    const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv);
+    if (lane == 0) {
+      if (ev_sum) atomicAdd(tally_slot(A, cc.run), ev_sum);
+      if (mv_sum) atomicAdd(tally_slot(A, cc.run) + 1, mv_sum);
+    }
+    if (errbits) atomicOr(rd->err, errbits);
+    wave_sync();  // LDS is rebuilt for the next chunk
+  }
+}
+
+// Event blocks (b of E): groups of K consecutive queue entries, group b,
+// b + E, ...; the listed tets of a group's tiles are packed CW to a chunk
+// (a chunk holds one run), so that tiles with one or two listed tets share
+// one pass of the SSA.
+template <int SMAX, int RMAX>
+__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued, int K,
+                                           EventLds<SMAX, RMAX>& L) {
+  constexpr int CW = EventLds<SMAX, RMAX>::CW;
+  const int lane = threadIdx.x;
   bool tables = false;
   int cache_run = -1;
   uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
+  const cptr<int> tile_run = as_const(reinterpret_cast<const int*>(A.tile_map));
+  const int n_groups = (n_queued + K - 1) / K;
 
-  for (int q = b; q < n_queued; q += E) {
-    const int tile = A.evq[q];
-    const int n_tile = A.wl_tile_count[tile];
-    for (int c0 = 0; c0 < n_tile; c0 += CW) {
-      const int n_work = n_tile - c0 < CW ? n_tile - c0 : CW;
-      const TileCtx cc = tile_ctx(A, tile, k);
-      const cptr<RunDesc> rd = cc.rd;
-      const int T = cc.T;
-      const double tau = cc.tau_k;
-
-      // the entry holds everything the tet needs: one round of loads
-      const bool active = lane < n_work;
-      const size_t e = (size_t)tile * kWave + (size_t)(c0 + lane);
-      int N[SMAX];
-      int i = 0;
-      double nav = 1.0;
-      int4 nb = make_int4(-1, -1, -1, -1);
-      double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
-      if (active) {
-        i = A.wl_tet[e];
-        nav = A.wl_nav[e];
-        nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
-        ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
-        gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
-      }
-      // tables and per-run constants: every load issued before any is used
-      const bool need_tables = !tables, need_run = cc.run != cache_run;
-      const bool regions = rd->region != nullptr;
-      const cptr<uint32_t> mw = as_const(reinterpret_cast<const uint32_t*>(A.model));
-      const cptr<uint32_t> kw = as_const(reinterpret_cast<const uint32_t*>(rd->kcst));
-      uint32_t d0 = 0, d1 = 0, dp = 0, kv[kMaxRegions];
-      double dv = 0.0;
-      int reg = 0;
-      if (need_tables) {
-        d0 = mw[offsetof(DevModel, delta) / 4 + lane];
-        d1 = mw[offsetof(DevModel, delta) / 4 + kWave + lane];
-        dp = mw[offsetof(DevModel, deps) / 4 + lane];
-      }
-      if (need_run) {
-#pragma unroll
-        for (int q = 0; q < kMaxRegions; ++q) kv[q] = (q == 0 || regions) ? kw[q * kWave + lane] : 0u;
-        if (lane < SMAX && lane < S) dv = rd->D[lane];
-      }
-      if (active && regions) reg = A.wl_reg[e];
-      if (need_tables) {
-        L.delta_w[lane] = d0;
-        L.delta_w[kWave + lane] = d1;
-        L.deps_w[lane] = dp;
-        tables = true;
-      }
-      if (need_run) {
-#pragma unroll
-        for (int q = 0; q < kMaxRegions; ++q)
-          if (q == 0 || regions) L.kc_w[q * kWave + lane] = kv[q];
-        if (lane < SMAX) L.td[lane] = lane < S ? tau * dv : 0.0;
-        dmask = (uint32_t)__ballot(lane < SMAX && lane < S && tau * dv > 0.0);
-        cache_run = cc.run;
-      }
-      wave_sync();
-      const double(*s_kc)[32] = reinterpret_cast<const double(*)[32]>(L.kc_w);
-
-      // the tet's neighbours and couplings wait in LDS while the SSA runs
-      L.tet[lane] = i;
-      L.nbr[lane] = nb;
-      L.geo[0][lane] = ga;
-      L.geo[1][lane] = gb;
-
-      unsigned long long n_ev = 0, n_mv = 0;
-      int errbits = 0;
-      uint32_t mask = 0;
-      double nbv[SMAX];  // mean occupancies of the tet's items
-      int npv[SMAX];     // post-reaction counts
-      if (active) {
-        // counts as one vector value (uniform species indices select
-        // registers); rate constants of the tet's region from LDS
-        int __attribute__((ext_vector_type(SMAX))) Nv;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) Nv[s] = N[s];
-        const double inv_nav = 1.0 / nav;
-        const double* kreg = s_kc[reg];
-        double* col = &L.a[0][lane];  // a_r at col[r * CW]
-#pragma unroll 1
-        for (int r = 0; r < R; ++r) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
-
-        // ---- reaction SSA operator over [0, tau_k] ----
-        double O[SMAX], tS[SMAX];
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          O[s] = 0.0;
-          tS[s] = 0.0;
+  for (int g = b; g < n_groups; g += E) {
+    // the group's tiles, listed counts and runs: lane j loads entry j (one
+    // round of loads for the whole group)
+    const int q0 = g * K;
+    const int nq = n_queued - q0 < K ? n_queued - q0 : K;
+    int g_tile = 0, g_n = 0, g_run = -1;
+    if (lane < nq) {
+      g_tile = A.evq[q0 + lane];
+      g_n = A.wl_tile_count[g_tile];
+      g_run = tile_run[2 * g_tile];
+    }
+    // walk the group's tiles and their listed tets in order; the chunk is
+    // run from one place in the code
+    int q = -1, tile = 0, n = 0, run = -1, j0 = 0;
+    int fill = 0, tile0 = 0, run0 = -1;
+    size_t slot = 0;
+    for (;;) {
+      if (j0 >= n) {  // the next tile of the group with listed tets
+        j0 = 0;
+        n = 0;
+        for (++q; q < nq; ++q) {
+          n = __builtin_amdgcn_readlane(g_n, q);
+          if (n > 0) break;
         }
-        uint32_t touched = 0;
-        Draw53 st(rd->key0, rd->key1, 0u, (uint32_t)i, cc.window);
-        double dt = 0.0;
-        unsigned int ev_tet = 0;
-        for (;;) {
-          double a0 = 0.0;
-#pragma unroll 4
-          for (int r = 0; r < R; ++r) a0 = a0 + col[r * CW];
-          if (!(a0 > 0.0)) break;
-          const double u = st.oc();
-          const double t_reac = -ln_basic(u) / a0;
-          if (dt + t_reac > tau) break;
-          const int rn = cr_select_col(col, CW, R, a0, st);
-          dt = dt + t_reac;
-          // few lanes of a wave are in the loop at a time, so branches that
-          // skip unchanged species and unaffected reactions are cheap
-          const uint4 drow = reinterpret_cast<const uint4*>(L.delta_w)[rn];
-          const unsigned long long dep = reinterpret_cast<const unsigned long long*>(L.deps_w)[rn];
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) {
-            if (s < S) {
-              const uint32_t wd = (s >> 2) == 0 ? drow.x : ((s >> 2) == 1 ? drow.y : ((s >> 2) == 2 ? drow.z : drow.w));
-              const int d = (int)(int8_t)((wd >> (8 * (s & 3))) & 0xffu);
-              if (d != 0) {
-                const int n = Nv[s];
-                O[s] = O[s] + (double)n * (dt - tS[s]);
-                tS[s] = dt;
-                touched |= 1u << s;
-                Nv[s] = n + d;
-                if (n + d > kCountCap) errbits |= kErrOverflow;
-              }
-            }
-          }
-          // the propensities that read a changed species
-#pragma unroll 1
-          for (int r = 0; r < R; ++r)
-            if ((dep >> r) & 1ull) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
-          ++ev_tet;
-          if (errbits) break;
-          if (ev_tet >= (unsigned int)kEventCap) {
-            errbits |= kErrEvents;
-            break;
-          }
-        }
-        n_ev = ev_tet;
-
-        // ---- mean occupancies; items for the diffusion operator ----
-        const bool coupled = L.geo[0][lane].x > 0.0;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          nbv[s] = 0.0;
-          npv[s] = 0;
-          if (s >= S) continue;
-          const int n = Nv[s];
-          const double occ = (O[s] + (double)n * (tau - tS[s])) / tau;
-          const double nbar = ((touched >> s) & 1u) ? occ : (double)n;
-          if (((dmask >> s) & 1u) && coupled && nbar > 0.0) {
-            mask |= 1u << s;
-            nbv[s] = nbar;
-            npv[s] = n;
-          } else if (n != 0) {
-            atomicAdd(cc.cout + (size_t)s * T + i, n);  // nothing can leave
-          }
-        }
-      } else {
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          nbv[s] = 0.0;
-          npv[s] = 0;
+        if (q < nq) {
+          tile = __builtin_amdgcn_readlane(g_tile, q);
+          run = __builtin_amdgcn_readlane(g_run, q);
         }
       }
-      const int cnt = __popc(mask);
-      const int incl = wave_inclusive_scan(cnt);
-      const int total = __shfl(incl, kWave - 1);
-      const int first = incl - cnt;
-      // items in rounds of 64: each lane parks the items of the round that
-      // are its own, then every lane samples one
-      for (int r0 = 0; r0 < total; r0 += kWave) {
-        int pos = first;
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) {
-          if ((mask >> s) & 1u) {
-            const unsigned slot = (unsigned)(pos - r0);
-            if (slot < (unsigned)kWave) {
-              L.item[slot] = (uint16_t)((lane << 4) | s);
-              L.nbar[slot] = nbv[s];
-              L.npost[slot] = npv[s];
-            }
-            ++pos;
-          }
-        }
-        wave_sync();
-        if (lane < total - r0) {
-          const int it = L.item[lane];
-          const int Ln = it >> 4, sp = it & 15;
-          const int ti = L.tet[Ln];
-          const int npost = L.npost[lane];
-          const int4 tnb = L.nbr[Ln];
-          const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[lane], npost,
-                                           tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
-          int32_t* out_s = cc.cout + (size_t)sp * T;
-          if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
-          if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
-          if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
-          if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
-          if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
-          n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
-        }
-        wave_sync();  // the round's LDS entries are rebuilt for the next
+      const bool done = q >= nq;
+      if (fill > 0 && (done || run != run0 || fill == CW)) {
+        event_chunk<SMAX, RMAX>(A, k, tile0, fill, slot, L, tables, cache_run, dmask);
+        fill = 0;
       }
-      const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv);
-      if (lane == 0) {
-        if (ev_sum) atomicAdd(tally_slot(A, cc.run), ev_sum);
-        if (mv_sum) atomicAdd(tally_slot(A, cc.run) + 1, mv_sum);
+      if (done) break;
+      if (fill == 0) {
+        tile0 = tile;
+        run0 = run;
       }
-      if (errbits) atomicOr(rd->err, errbits);
-      wave_sync();  // LDS is rebuilt for the next tile
+      const int take = n - j0 < CW - fill ? n - j0 : CW - fill;
+      if (lane >= fill && lane < fill + take) slot = (size_t)tile * kWave + (size_t)(j0 + lane - fill);
+      fill += take;
+      j0 += take;
     }
   }
 }
@@ -1058,18 +1119,25 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 window_main_kernel(const StepArgs A) {
   __shared__ MainLds<SMAX, RMAX> lds;
   const int k = step_index(A);
-  const int n_queued = __builtin_amdgcn_readfirstlane(A.evq_count[k & 1]);
+  const unsigned long long qc = *as_const(A.evq_count + (k & 1));
+  const int n_queued = __builtin_amdgcn_readfirstlane((int)(qc & 0xffffffffull));
+  const int n_listed = __builtin_amdgcn_readfirstlane((int)(qc >> 32));
   if (blockIdx.x == 0 && threadIdx.x == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
-  // event blocks: one per queued tile, a multiple of the 8 XCDs (so that the
-  // diffusion blocks keep their XCD mapping), at most half the grid
+  // event blocks: one per group of K queued tiles, K chosen so that a group
+  // lists about 64 tets, at most 4 tiles (longer groups make the event blocks
+  // the last to finish); a multiple of the 8 XCDs (so that the diffusion
+  // blocks keep their XCD mapping), at most half the grid
   const int G = gridDim.x;
-  int E = 0;
+  int E = 0, K = 1;
   if (n_queued > 0) {
+    K = n_listed > 0 ? (int)((64ll * n_queued) / n_listed) : 1;
+    K = K < 1 ? 1 : (K > 4 ? 4 : K);
+    const int n_groups = (n_queued + K - 1) / K;
     const int cap = G / 2 >= 8 ? (G / 2) & ~7 : (G / 2 > 0 ? G / 2 : 1);
-    E = (n_queued + 7) & ~7;
+    E = (n_groups + 7) & ~7;
     if (E > cap) E = cap;
   }
-  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, lds.e);
+  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, K, lds.e);
   else diffusion_part<SMAX, RMAX>(A, k, (int)blockIdx.x - E, G - E, lds.d);
 }
 

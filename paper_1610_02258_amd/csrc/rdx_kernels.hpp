@@ -76,7 +76,7 @@ struct StepArgs {
   unsigned long long* wl_mask; // [tiles] listed tets of each tile (bit = lane)
   int32_t* wl_tile_count;      // [tiles], valid for the tiles in the queue
   int32_t* evq;                // [tiles] queue of the tiles with listed tets
-  int32_t* evq_count;          // [2] queue lengths by step parity
+  unsigned long long* evq_count;  // [2] by step parity: queued tiles (low word), their listed tets (high word)
   int32_t* wl_tet;
   uint8_t* wl_reg;             // region label
   int32_t* wl_cnt;             // [S][wl_stride]
