@@ -219,7 +219,8 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
             dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
-            dev_alloc(&evq_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&evq_count_, 2) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
+            dev_alloc(&evq_, (size_t)kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
+            dev_alloc(&evq_count_, (size_t)2 * kQueues * kQueueStride) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
             dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
             dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
@@ -237,7 +238,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
-  RDX_HIP(hipMemset(evq_count_, 0, 2 * sizeof(unsigned long long)));
+  RDX_HIP(hipMemset(evq_count_, 0, sizeof(unsigned long long) * 2 * kQueues * kQueueStride));
   RDX_HIP(hipDeviceSynchronize());
   return RDX_OK;
 }
@@ -571,6 +572,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   }
   a.wl_tile_count = wl_tile_count_;
   a.evq = evq_;
+  a.evq_cap = (int32_t)((max_tiles_ + kQueues - 1) / kQueues);
   a.evq_count = evq_count_;
   a.wl_tet = wl_tet_;
   a.wl_reg = wl_reg_;

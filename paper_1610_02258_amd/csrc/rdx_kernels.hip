@@ -354,6 +354,17 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
   return acc;
 }
 
+// Inclusive prefix sum over the 64 lanes for any int (six shuffle steps).
+__device__ __forceinline__ int wave_scan_add(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int u = __shfl_up(v, d, kWave);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
 // Leavers of one item and their faces.  m = nbar stochastically rounded (a
 // draw only when nbar is fractional).  With m <= 16 every molecule draws one
 // 32-bit uniform u and leaves when u < p, to the first face k before the last
@@ -615,11 +626,14 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
       A.wl_mask[tile] = ballot;
       if (ballot) {
         A.wl_tile_count[tile] = (int)__popcll(ballot);
-        // one atomic counts the queued tile (low word) and its listed tets
-        // (high word); the old low word is the tile's queue slot
+        // one atomic on the tile's sub-queue counts the queued tile (low
+        // word) and its listed tets (high word); the old low word is the
+        // tile's slot in that sub-queue
+        const int qj = tile & (kQueues - 1);
         const unsigned long long old =
-            atomicAdd(A.evq_count + (k & 1), ((unsigned long long)__popcll(ballot) << 32) | 1ull);
-        A.evq[(int)(old & 0xffffffffull)] = tile;
+            atomicAdd(A.evq_count + ((size_t)(k & 1) * kQueues + qj) * kQueueStride,
+                      ((unsigned long long)__popcll(ballot) << 32) | 1ull);
+        A.evq[(size_t)qj * A.evq_cap + (size_t)(old & 0xffffffffull)] = tile;
       }
     }
     if (event) {  // the tile's listed tets take its own worklist slots
@@ -1055,7 +1069,7 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
 // one pass of the SSA.
 template <int SMAX, int RMAX>
 __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued, int K,
-                                           EventLds<SMAX, RMAX>& L) {
+                                           int q_incl, EventLds<SMAX, RMAX>& L) {
   constexpr int CW = EventLds<SMAX, RMAX>::CW;
   const int lane = threadIdx.x;
   bool tables = false;
@@ -1069,9 +1083,16 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
     // round of loads for the whole group)
     const int q0 = g * K;
     const int nq = n_queued - q0 < K ? n_queued - q0 : K;
+    // entry q is slot q - (tiles of the sub-queues before j) of sub-queue j,
+    // j the first sub-queue whose inclusive prefix exceeds q
     int g_tile = 0, g_n = 0, g_run = -1;
+    for (int l = 0; l < nq; ++l) {
+      const int q = q0 + l;
+      const int j = (int)__popcll(__ballot(q_incl <= q));
+      const int before = j > 0 ? __builtin_amdgcn_readlane(q_incl, j - 1) : 0;
+      if (lane == l) g_tile = A.evq[(size_t)j * A.evq_cap + (size_t)(q - before)];
+    }
     if (lane < nq) {
-      g_tile = A.evq[q0 + lane];
       g_n = A.wl_tile_count[g_tile];
       g_run = tile_run[2 * g_tile];
     }
@@ -1119,10 +1140,16 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 window_main_kernel(const StepArgs A) {
   __shared__ MainLds<SMAX, RMAX> lds;
   const int k = step_index(A);
-  const unsigned long long qc = *as_const(A.evq_count + (k & 1));
-  const int n_queued = __builtin_amdgcn_readfirstlane((int)(qc & 0xffffffffull));
-  const int n_listed = __builtin_amdgcn_readfirstlane((int)(qc >> 32));
-  if (blockIdx.x == 0 && threadIdx.x == 0) A.evq_count[(k + 1) & 1] = 0;  // the next window's queue starts empty
+  // the sub-queues: lane j holds sub-queue j's tiles and their inclusive
+  // prefix sum over the sub-queues
+  const int lane = threadIdx.x;
+  const unsigned long long qc = A.evq_count[((size_t)(k & 1) * kQueues + lane) * kQueueStride];
+  const int q_n = (int)(qc & 0xffffffffull);
+  const int q_incl = wave_scan_add(q_n);
+  const int n_queued = __builtin_amdgcn_readlane(q_incl, kWave - 1);
+  const int n_listed = __builtin_amdgcn_readlane(wave_scan_add((int)(qc >> 32)), kWave - 1);
+  if (blockIdx.x == 0)  // the next window's queue starts empty
+    A.evq_count[((size_t)((k + 1) & 1) * kQueues + lane) * kQueueStride] = 0;
   // event blocks: one per group of K queued tiles, K chosen so that a group
   // lists about 64 tets, at most 4 tiles (longer groups make the event blocks
   // the last to finish); a multiple of the 8 XCDs (so that the diffusion
@@ -1137,7 +1164,7 @@ window_main_kernel(const StepArgs A) {
     E = (n_groups + 7) & ~7;
     if (E > cap) E = cap;
   }
-  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, K, lds.e);
+  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, K, q_incl, lds.e);
   else diffusion_part<SMAX, RMAX>(A, k, (int)blockIdx.x - E, G - E, lds.d);
 }
 

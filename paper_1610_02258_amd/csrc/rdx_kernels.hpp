@@ -75,8 +75,13 @@ struct StepArgs {
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
   unsigned long long* wl_mask; // [tiles] listed tets of each tile (bit = lane)
   int32_t* wl_tile_count;      // [tiles], valid for the tiles in the queue
-  int32_t* evq;                // [tiles] queue of the tiles with listed tets
-  unsigned long long* evq_count;  // [2] by step parity: queued tiles (low word), their listed tets (high word)
+  // queue of the tiles with listed tets, in kQueues sub-queues (tile t goes
+  // to sub-queue t mod kQueues, slots q * evq_cap ...) so that no counter is
+  // contended by every tile
+  int32_t* evq;                // [kQueues][evq_cap]
+  int32_t evq_cap;
+  unsigned long long* evq_count;  // [2][kQueues][16] by step parity, one 128-byte line per counter:
+                                  // queued tiles (low word), their listed tets (high word)
   int32_t* wl_tet;
   uint8_t* wl_reg;             // region label
   int32_t* wl_cnt;             // [S][wl_stride]
@@ -84,6 +89,9 @@ struct StepArgs {
   int32_t* wl_nbr;             // [wl_stride][4]
   double* wl_geo;              // [wl_stride][4]
 };
+
+constexpr int kQueues = 64;
+constexpr int kQueueStride = 16;  // u64 per counter line
 
 // Tallies are spread over this many slots per run (block b adds to slot
 // b mod kTallySlots), so that blocks finishing together do not queue on one
