@@ -168,7 +168,10 @@ size_t Engine::run_bytes(const HostInstance& I) {
   return b;
 }
 
-size_t Engine::worklist_bytes_per_tet(int S) { return 4 + 1 + 4 * (size_t)S + 8 + 16 + 32 + 1; }
+size_t Engine::worklist_bytes_per_tet(int S) {
+  (void)S;
+  return 4 + 1;  // the tet index of its slot, and its share of the per-tile count and queue entry
+}
 
 Engine::~Engine() {
   if (staged_) (void)hipEventSynchronize(staged_);
@@ -188,11 +191,6 @@ Engine::~Engine() {
   (void)hipFree(evq_);
   (void)hipFree(evq_count_);
   (void)hipFree(wl_tet_);
-  (void)hipFree(wl_reg_);
-  (void)hipFree(wl_cnt_);
-  (void)hipFree(wl_nav_);
-  (void)hipFree(wl_nbr_);
-  (void)hipFree(wl_geo_);
   if (h_runs_) (void)hipHostFree(h_runs_);
   if (h_tile_map_) (void)hipHostFree(h_tile_map_);
   if (h_n_tiles_) (void)hipHostFree(h_n_tiles_);
@@ -220,9 +218,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
             dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&evq_, (size_t)kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
-            dev_alloc(&evq_count_, (size_t)2 * kQueues * kQueueStride) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&wl_reg_, W) == hipSuccess &&
-            dev_alloc(&wl_cnt_, (size_t)S_ * W) == hipSuccess && dev_alloc(&wl_nav_, W) == hipSuccess &&
-            dev_alloc(&wl_nbr_, 4 * W) == hipSuccess && dev_alloc(&wl_geo_, 4 * W) == hipSuccess;
+            dev_alloc(&evq_count_, (size_t)2 * kQueues * kQueueStride) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
@@ -563,7 +559,6 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.S = S_;
   a.R = R_;
   a.wl_mask = wl_mask_;
-  a.wl_stride = (int32_t)(64 * max_tiles_);
   a.model = model_;
   std::memcpy(a.info, model_host_.info, sizeof a.info);
   {
@@ -575,11 +570,6 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.evq_cap = (int32_t)((max_tiles_ + kQueues - 1) / kQueues);
   a.evq_count = evq_count_;
   a.wl_tet = wl_tet_;
-  a.wl_reg = wl_reg_;
-  a.wl_cnt = wl_cnt_;
-  a.wl_nav = wl_nav_;
-  a.wl_nbr = wl_nbr_;
-  a.wl_geo = wl_geo_;
 
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
     grids_for(n_tiles, sh.fast_grid_div, &a.detect_grid, &a.main_grid);

@@ -176,11 +176,6 @@ class Engine {
   int32_t* evq_ = nullptr;
   unsigned long long* evq_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
-  uint8_t* wl_reg_ = nullptr;
-  int32_t* wl_cnt_ = nullptr;
-  double* wl_nav_ = nullptr;
-  int32_t* wl_nbr_ = nullptr;
-  double* wl_geo_ = nullptr;
 
   // pinned staging of the run table and tile map; `staged_` marks the
   // completion of the last upload from them

@@ -639,15 +639,6 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
     if (event) {  // the tile's listed tets take its own worklist slots
       const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
       A.wl_tet[slot] = i;
-      A.wl_nav[slot] = nav;
-      A.wl_reg[slot] = (uint8_t)reg;
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s < S) A.wl_cnt[(size_t)s * A.wl_stride + slot] = Nc[s];
-      reinterpret_cast<int4*>(A.wl_nbr)[slot] = ld_int4(reinterpret_cast<const int4*>(rd->nbr), (size_t)i);
-      reinterpret_cast<double2*>(A.wl_geo)[2 * slot] = ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i);
-      reinterpret_cast<double2*>(A.wl_geo)[2 * slot + 1] =
-          ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i + 1);
     }
     cc = nc;
     cur = nxt;
@@ -825,7 +816,9 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
         for (int s = 0; s < SMAX; ++s) {
           if (s < S) {
             if (v[s] != 0) atomicAdd(cc.cout + (size_t)s * T + i, v[s]);
-            cc.cin[(size_t)s * T + i] = 0;  // the target of the window after next
+            // the target of the window after next (a listed tet's counts are
+            // read and cleared by its event block)
+            if (!event) cc.cin[(size_t)s * T + i] = 0;
           }
         }
       }
@@ -859,23 +852,24 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
     const int T = cc.T;
     const double tau = cc.tau_k;
 
-    // the entry holds everything the tet needs: one round of loads
+    // the worklist entry names the tet; its counts, N_A V, region,
+    // neighbours and couplings are read in place (the diffusion blocks leave
+    // a listed tet's counts alone), then its counts are cleared for the
+    // window after next
     const bool active = lane < n_work;
-    const size_t e = slot;
     int N[SMAX];
     int i = 0;
     double nav = 1.0;
     int4 nb = make_int4(-1, -1, -1, -1);
     double2 ga = make_double2(0.0, 0.0), gb = make_double2(0.0, 0.0);
+    if (active) i = A.wl_tet[slot];
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      N[s] = (active && s < S) ? A.wl_cnt[(size_t)s * A.wl_stride + e] : 0;
+    for (int s = 0; s < SMAX; ++s) N[s] = (active && s < S) ? cc.cin[(size_t)s * T + i] : 0;
     if (active) {
-      i = A.wl_tet[e];
-      nav = A.wl_nav[e];
-      nb = reinterpret_cast<const int4*>(A.wl_nbr)[e];
-      ga = reinterpret_cast<const double2*>(A.wl_geo)[2 * e];
-      gb = reinterpret_cast<const double2*>(A.wl_geo)[2 * e + 1];
+      nav = as_const(rd->nav)[i];
+      nb = ld_int4(reinterpret_cast<const int4*>(rd->nbr), (size_t)i);
+      ga = ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i);
+      gb = ld_double2(reinterpret_cast<const double2*>(rd->geo), 2 * (size_t)i + 1);
     }
     // tables and per-run constants: every load issued before any is used
     const bool need_tables = !tables, need_run = cc.run != cache_run;
@@ -895,7 +889,7 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
       for (int q = 0; q < kMaxRegions; ++q) kv[q] = (q == 0 || regions) ? kw[q * kWave + lane] : 0u;
       if (lane < SMAX && lane < S) dv = rd->D[lane];
     }
-    if (active && regions) reg = A.wl_reg[e];
+    if (active && regions) reg = as_const(rd->region)[i];
     if (need_tables) {
       L.delta_w[lane] = d0;
       L.delta_w[kWave + lane] = d1;
@@ -935,6 +929,10 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
       double* col = &L.a[0][lane];  // a_r at col[r * CW]
 #pragma unroll 1
       for (int r = 0; r < R; ++r) col[r * CW] = propensity<SMAX>(A.info[r], kreg[r], Nv, nav, inv_nav);
+      // the counts are in registers now; clear them for the window after next
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s < S) cc.cin[(size_t)s * T + i] = 0;
 
       // ---- reaction SSA operator over [0, tau_k] ----
       double O[SMAX], tS[SMAX];

@@ -66,7 +66,6 @@ struct StepArgs {
   int32_t S, R;
   int32_t detect_grid;         // persistent grid of the detect kernel
   int32_t main_grid;           // grid of the main kernel (event blocks + persistent diffusion blocks), >= 2
-  int32_t wl_stride;           // worklist capacity, 64 entries per tile (row stride of wl_cnt)
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
   int32_t n_pairs;             // distinct reactant pairs of the second-order reactions
@@ -83,11 +82,6 @@ struct StepArgs {
   unsigned long long* evq_count;  // [2][kQueues][16] by step parity, one 128-byte line per counter:
                                   // queued tiles (low word), their listed tets (high word)
   int32_t* wl_tet;
-  uint8_t* wl_reg;             // region label
-  int32_t* wl_cnt;             // [S][wl_stride]
-  double* wl_nav;
-  int32_t* wl_nbr;             // [wl_stride][4]
-  double* wl_geo;              // [wl_stride][4]
 };
 
 constexpr int kQueues = 64;

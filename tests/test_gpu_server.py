@@ -47,8 +47,8 @@ def _solo(rdx, w):
 def test_results_equal_alone_and_in_the_mix(rdx, oracle_lib):
     reqs = _requests(14, seed=21)
     sizes = [w.mesh.n_tets for _, w in reqs]
-    _say(f"case: server, 14 requests, T = {sizes}, 8 MiB budget")
-    srv = rdx.Server(reqs[0][1].model.as_dict(), hbm_budget_bytes=8 << 20, tick_windows=4)
+    _say(f"case: server, 14 requests, T = {sizes}, 4 MiB budget")
+    srv = rdx.Server(reqs[0][1].model.as_dict(), hbm_budget_bytes=4 << 20, tick_windows=4)
     tickets = []
     for arrival, w in reqs:
         tickets.append(srv.submit(w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts, w.t_end))
