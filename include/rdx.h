@@ -185,11 +185,14 @@ rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
  *                  the fastest; get returns 1 while tuning is under way
  *   fast_grid_div  main kernel grid = resident grid / this (1, 2 or 4)
  *   graph_windows  windows per captured HIP graph, replayed as one launch;
- *                  1 = plain launches (1..256) */
+ *                  1 = plain launches (1..256)
+ *   event_group    most queued tiles whose listed tets one event block packs
+ *                  into one 64-lane chunk (1..8; 0 = the default, 4) */
 typedef struct rdx_exec_options {
   int32_t autotune;
   int32_t fast_grid_div;
   int32_t graph_windows;
+  int32_t event_group;
 } rdx_exec_options;
 
 rdx_status rdx_set_exec_options(rdx_sim* sim, const rdx_exec_options* opts);
@@ -317,7 +320,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 200
+#define RDX_ABI_VERSION 201
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -96,9 +96,10 @@ rdx_status fill_stats(Engine& eng, const Run& r, rdx_stats* out) {
 rdx_status apply_options(Engine& eng, const rdx_exec_options* o) {
   if (!o) return set_error(RDX_EINVAL, "null options");
   if (!(o->fast_grid_div == 1 || o->fast_grid_div == 2 || o->fast_grid_div == 4) || o->graph_windows < 1 ||
-      o->graph_windows > 256)
-    return set_error(RDX_EINVAL, "fast_grid_div must be 1, 2 or 4 and graph_windows in [1, 256]");
-  eng.set_shape(ExecShape{o->fast_grid_div, o->graph_windows});
+      o->graph_windows > 256 || o->event_group < 0 || o->event_group > 8)
+    return set_error(RDX_EINVAL,
+                     "fast_grid_div must be 1, 2 or 4, graph_windows in [1, 256], event_group in [0, 8]");
+  eng.set_shape(ExecShape{o->fast_grid_div, o->graph_windows, o->event_group ? o->event_group : 4});
   if (o->autotune) eng.set_autotune(true);
   return RDX_OK;
 }
@@ -107,6 +108,7 @@ void read_options(const Engine& eng, rdx_exec_options* o) {
   o->autotune = eng.tuning() ? 1 : 0;
   o->fast_grid_div = eng.shape().fast_grid_div;
   o->graph_windows = eng.shape().graph_windows;
+  o->event_group = eng.shape().event_group;
 }
 
 }  // namespace

@@ -490,7 +490,7 @@ rdx_status Engine::launch_plain(const StepArgs& a0, int64_t K, hipStream_t strea
 
 rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t stream) {
   const int W = shape_.graph_windows;
-  const auto key = std::make_pair(W, a0.main_grid * 65536 + a0.detect_grid);
+  const auto key = std::make_pair(W, (a0.main_grid * 65536 + a0.detect_grid) * 16 + a0.ev_group_max);
   auto it = graphs_.find(key);
   if (it == graphs_.end()) {
     if (graphs_.size() >= 16) free_graphs();
@@ -524,8 +524,8 @@ void Engine::set_autotune(bool on) {
   cand_next_ = 0;
   if (!on) return;
   // the first entry is a warm-up of the default shape and is not scored
-  candidates_ = {ExecShape{1, 1}, ExecShape{1, 1}, ExecShape{2, 1}, ExecShape{1, 8}, ExecShape{2, 8},
-                 ExecShape{4, 8}};
+  candidates_ = {ExecShape{1, 1, 4}, ExecShape{1, 1, 4}, ExecShape{2, 1, 4}, ExecShape{1, 8, 4},
+                 ExecShape{2, 8, 4}, ExecShape{4, 8, 4}, ExecShape{1, 8, 1}, ExecShape{1, 8, 8}};
 }
 
 rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
@@ -573,6 +573,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
 
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
     grids_for(n_tiles, sh.fast_grid_div, &a.detect_grid, &a.main_grid);
+    a.ev_group_max = sh.event_group;
     const ExecShape keep = shape_;
     shape_ = sh;
     rdx_status r = RDX_OK;
@@ -593,6 +594,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
     const int64_t n = std::min<int64_t>(K - done, std::max(8, 2 * c.graph_windows));
     if (c.graph_windows > 1 && n >= c.graph_windows) {  // capture outside the timed span
       grids_for(n_tiles, c.fast_grid_div, &a.detect_grid, &a.main_grid);
+      a.ev_group_max = c.event_group;
       const ExecShape keep = shape_;
       shape_ = c;
       st = launch_graphs(a, 0, stream);

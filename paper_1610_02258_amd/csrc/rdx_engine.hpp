@@ -81,9 +81,11 @@ struct Run {
 struct ExecShape {
   int fast_grid_div = 1;
   int graph_windows = 1;
+  int event_group = 4;  // most queued tiles packed into one event chunk
   bool operator<(const ExecShape& o) const {
-    return fast_grid_div != o.fast_grid_div ? fast_grid_div < o.fast_grid_div
-                                            : graph_windows < o.graph_windows;
+    if (fast_grid_div != o.fast_grid_div) return fast_grid_div < o.fast_grid_div;
+    if (graph_windows != o.graph_windows) return graph_windows < o.graph_windows;
+    return event_group < o.event_group;
   }
 };
 

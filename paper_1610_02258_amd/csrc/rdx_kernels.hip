@@ -1149,14 +1149,16 @@ window_main_kernel(const StepArgs A) {
   if (blockIdx.x == 0)  // the next window's queue starts empty
     A.evq_count[((size_t)((k + 1) & 1) * kQueues + lane) * kQueueStride] = 0;
   // event blocks: one per group of K queued tiles, K chosen so that a group
-  // lists about 64 tets, at most 4 tiles (longer groups make the event blocks
-  // the last to finish); a multiple of the 8 XCDs (so that the diffusion
-  // blocks keep their XCD mapping), at most half the grid
+  // lists about 64 tets, at most ev_group_max tiles (a launch-shape setting:
+  // longer groups can make the event blocks the last to finish); a multiple
+  // of the 8 XCDs (so that the diffusion blocks keep their XCD mapping), at
+  // most half the grid
   const int G = gridDim.x;
   int E = 0, K = 1;
   if (n_queued > 0) {
     K = n_listed > 0 ? (int)((64ll * n_queued) / n_listed) : 1;
-    K = K < 1 ? 1 : (K > 4 ? 4 : K);
+    const int K_max = A.ev_group_max >= 1 ? A.ev_group_max : 1;
+    K = K < 1 ? 1 : (K > K_max ? K_max : K);
     const int n_groups = (n_queued + K - 1) / K;
     const int cap = G / 2 >= 8 ? (G / 2) & ~7 : (G / 2 > 0 ? G / 2 : 1);
     E = (n_groups + 7) & ~7;

@@ -260,7 +260,7 @@ rdx_status rdx_server_create(const rdx_model* structure, const rdx_server_option
   st = s->eng.init(proto, arena, max_runs, cap);
   if (st != RDX_OK) return st;
   const int gw = opts->graph_windows ? opts->graph_windows : s->tick_windows;
-  s->eng.set_shape(ExecShape{1, gw});
+  s->eng.set_shape(ExecShape{1, gw, 4});
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     return set_error(RDX_EHIP, "stream creation failed");
   s->t0 = std::chrono::steady_clock::now();

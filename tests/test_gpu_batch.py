@@ -59,9 +59,9 @@ def _assert_run(b, i, ref, what):
     assert st.window_index == ref.window and st.t == ref.t, (what, i)
 
 
-@pytest.mark.parametrize("shape", [dict(fast_grid_div=1, graph_windows=1),
+@pytest.mark.parametrize("shape", [dict(fast_grid_div=1, graph_windows=1, event_group=1),
                                    dict(fast_grid_div=2, graph_windows=4),
-                                   dict(fast_grid_div=4, graph_windows=8),
+                                   dict(fast_grid_div=4, graph_windows=8, event_group=8),
                                    dict(autotune=True)])
 def test_batch_matches_oracle_runs(rdx, oracle_lib, shape):
     runs = _small_ensemble()
@@ -184,5 +184,14 @@ def test_batch_options_validation(rdx):
         b.set_exec_options(fast_grid_div=3)
     with pytest.raises(rdx.RdxError):
         b.set_exec_options(graph_windows=0)
+    with pytest.raises(rdx.RdxError):
+        b.set_exec_options(event_group=9)
     b.set_exec_options(fast_grid_div=2, graph_windows=16)
-    assert b.exec_options() == dict(autotune=0, fast_grid_div=2, graph_windows=16)
+    assert b.exec_options() == dict(autotune=0, fast_grid_div=2, graph_windows=16, event_group=4)
+    b.set_exec_options(event_group=2)
+    assert b.exec_options()["event_group"] == 2
+    # the tuner's choice is one of its candidates and is kept once tuning ends
+    b.set_exec_options(autotune=True)
+    b.step(300)  # enough windows for every candidate
+    o = b.exec_options()
+    assert o["autotune"] == 0 and o["event_group"] in (1, 4, 8) and o["fast_grid_div"] in (1, 2, 4)
