@@ -284,17 +284,17 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // A window of a batch is two launches, one wave (64 lanes) per block, one lane
 // per tet, 64 tets per tile (a tile belongs to one run).
 //
-// window_detect_kernel, over all tiles: the propensities and their sum a0,
-// and the tet's first SSA waiting time.  A tet whose first event falls inside
-// the window is listed (its counts and mesh data go to the tile's worklist
-// slots, the tile to a queue); a per-tile bit mask marks the listed tets.
+// window_detect_kernel, over all tiles: a0 from regrouped coefficients and the
+// tet's first SSA uniform.  A tet whose first event may fall inside the
+// window is listed (its index goes to the tile's worklist slots, the tile to
+// one of 64 sub-queues); a per-tile bit mask marks the listed tets.
 //
-// window_main_kernel: its first blocks take the queued tiles and run the full
-// SSA window (composition-rejection, occupancy) and the diffusion of the
-// listed tets; the other blocks walk all tiles and do the diffusion of every
-// tet that is not listed (no count changes, the mean occupancy is the count
-// itself).  The serial SSA chains of the few listed tets so run alongside the
-// bandwidth-bound diffusion of the rest instead of after it.
+// window_main_kernel: its first blocks take groups of queued tiles and run
+// the full SSA window (composition-rejection, occupancy) and the diffusion of
+// the listed tets; the other blocks walk all tiles and do the diffusion of
+// every tet that is not listed (no count changes, the mean occupancy is the
+// count itself).  The serial SSA chains of the few listed tets so run
+// alongside the bandwidth-bound diffusion of the rest instead of after it.
 //
 // Diffusion items: every (tet, species) pair with something to sample becomes
 // an item; a wave-level prefix sum over the lanes' item counts packs them into
@@ -540,9 +540,6 @@ __device__ __forceinline__ void load_counts(const TileCtx& c, int S, int i, TetC
   d.reg = (active && c.rd->region) ? (int)as_const(c.rd->region)[i] : 0;
 }
 
-// Persistent: each block walks its tiles, the next tile's loads in flight
-// while the current one is worked on.  Values that depend only on the run
-// (rate constants, the key) are fetched once per run change.
 // a_0 of one tet from the regrouped listing coefficients of its region (`lc`,
 // a scalar pointer when the run has one region, a per-lane one otherwise).
 // The terms are those of the reaction-by-reaction sum, so the result agrees
@@ -566,8 +563,9 @@ __device__ __forceinline__ double listing_rate(const StepArgs& A, P lc, const NV
   return __builtin_fma(inv_nav, quad, lin);
 }
 
-// Persistent: each block walks its tiles, the next tile's loads in flight
-// while the current one is worked on.
+// One block per tile by default (the grid may also be smaller: a block then
+// walks its tiles, the next tile's loads in flight while the current one is
+// worked on).
 template <int SMAX, int RMAX>
 __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) {
   const int lane = threadIdx.x;
