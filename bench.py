@@ -105,8 +105,7 @@ def batched_leg(steps: int = 2) -> dict:
     t_end = [w.t_end for w in runs]
 
     def batch_step():
-        for i in range(len(runs)):
-            b.set_counts(i, c0[i], stream=stream)
+        b.set_counts_all(c0, stream=stream)  # every run reset in one launch
         b.run(t_end, stream=stream)
 
     batch_step()  # warm-up; also the online tuning of the launch shape

@@ -226,6 +226,13 @@ rdx_status rdx_batch_set_counts(rdx_batch* batch, int32_t i, const int32_t* coun
                                 void* stream);
 rdx_status rdx_batch_get_counts(rdx_batch* batch, int32_t i, int32_t* out, int is_device_ptr,
                                 void* stream);
+/* rdx_batch_set_counts for every run at once, from device memory, in one
+ * launch: counts[i] is a device pointer to run i's [n_species*n_tets] int32
+ * counts (caller-owned, alive until `stream` reaches the call); the host
+ * array `counts` itself is read during the call.  Every run restarts at t = 0,
+ * window 0, tallies cleared.  Errors: RDX_EINVAL (null pointer), RDX_EHIP. */
+rdx_status rdx_batch_set_counts_all(rdx_batch* batch, const int32_t* const* counts /* [n_runs] */,
+                                    void* stream);
 /* Algorithm 1 for every run i from its t to t_end[i] (as rdx_run); the
  * windows of all runs are enqueued together on `stream`. */
 rdx_status rdx_batch_run(rdx_batch* batch, const double* t_end /* [n_runs] */, void* stream);
@@ -320,7 +327,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 201
+#define RDX_ABI_VERSION 202
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -433,6 +433,17 @@ rdx_status rdx_batch_set_counts(rdx_batch* b, int32_t i, const int32_t* counts, 
   return start_run(b->eng, b->runs[(size_t)i], counts, is_device_ptr != 0, reinterpret_cast<hipStream_t>(stream));
 }
 
+rdx_status rdx_batch_set_counts_all(rdx_batch* b, const int32_t* const* counts, void* stream) {
+  clear_error();
+  if (!b || !counts) return set_error(RDX_EINVAL, "null argument");
+  for (size_t i = 0; i < b->runs.size(); ++i)
+    if (!counts[i]) return set_error(RDX_EINVAL, "null counts for run " + std::to_string(i));
+  (void)hipSetDevice(b->device);
+  std::vector<Run*> rs(b->runs.size());
+  for (size_t i = 0; i < b->runs.size(); ++i) rs[i] = &b->runs[i];
+  return b->eng.reset_runs_device(rs.data(), rs.size(), counts, reinterpret_cast<hipStream_t>(stream));
+}
+
 rdx_status rdx_batch_get_counts(rdx_batch* b, int32_t i, int32_t* out, int is_device_ptr, void* stream) {
   clear_error();
   if (check_batch_run(b, i) != RDX_OK) return RDX_EINVAL;

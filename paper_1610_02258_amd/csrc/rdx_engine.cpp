@@ -179,6 +179,12 @@ Engine::~Engine() {
   if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
   for (hipEvent_t e : marks_) (void)hipEventDestroy(e);
   if (staged_) (void)hipEventDestroy(staged_);
+  if (reset_staged_) {
+    (void)hipEventSynchronize(reset_staged_);
+    (void)hipEventDestroy(reset_staged_);
+  }
+  if (h_reset_) (void)hipHostFree(h_reset_);
+  (void)hipFree(d_reset_);
   for (hipEvent_t e : tune_ev_)
     if (e) (void)hipEventDestroy(e);
   (void)hipFree(model_);
@@ -327,6 +333,50 @@ rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
   RDX_HIP(hipMemsetAsync(r->cnt[(r->window + 1) & 1], 0, sizeof(int32_t) * n, stream));
   RDX_HIP(hipMemsetAsync(r->tally, 0, sizeof(unsigned long long) * 2 * kTallySlots, stream));
   RDX_HIP(hipMemsetAsync(r->err, 0, sizeof(int32_t), stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::reset_runs_device(Run* const* runs, size_t n, const int32_t* const* src, hipStream_t stream) {
+  size_t n_chunks = 0;
+  for (size_t j = 0; j < n; ++j) {
+    const int64_t e = (int64_t)runs[j]->host.S * runs[j]->host.T;
+    n_chunks += (size_t)std::max<int64_t>(1, (e + kResetChunk - 1) / kResetChunk);
+  }
+  if (n_chunks > (size_t)INT32_MAX) return set_error(RDX_EINVAL, "reset too large");
+  if (!reset_staged_) RDX_HIP(hipEventCreateWithFlags(&reset_staged_, hipEventDisableTiming));
+  RDX_HIP(hipEventSynchronize(reset_staged_));  // the pinned table may still be in flight
+  if (n_chunks > reset_cap_) {
+    if (h_reset_) RDX_HIP(hipHostFree(h_reset_));
+    if (d_reset_) RDX_HIP(hipFree(d_reset_));
+    h_reset_ = nullptr;
+    d_reset_ = nullptr;
+    reset_cap_ = 0;
+    RDX_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_reset_), sizeof(ResetChunk) * n_chunks));
+    RDX_HIP(hipMalloc(reinterpret_cast<void**>(&d_reset_), sizeof(ResetChunk) * n_chunks));
+    reset_cap_ = n_chunks;
+  }
+  size_t c = 0;
+  for (size_t j = 0; j < n; ++j) {
+    Run* r = runs[j];
+    if (r->arena_off == SIZE_MAX) return set_error(RDX_ESTATE, "run is not resident");
+    r->t = 0.0;
+    r->window = r->windows_run = r->voxel_steps = 0;
+    const int64_t e = (int64_t)r->host.S * r->host.T;
+    for (int64_t b = 0; b == 0 || b < e; b += kResetChunk) {
+      ResetChunk& ch = h_reset_[c++];
+      ch.src = src[j];
+      ch.dst = r->cnt[0];
+      ch.other = r->cnt[1];
+      ch.tally = r->tally;
+      ch.err = r->err;
+      ch.begin = b;
+      ch.end = std::min<int64_t>(b + kResetChunk, e);
+    }
+  }
+  RDX_HIP(hipMemcpyAsync(d_reset_, h_reset_, sizeof(ResetChunk) * c, hipMemcpyHostToDevice, stream));
+  RDX_HIP(hipEventRecord(reset_staged_, stream));
+  const hipError_t e = launch_reset_chunks(d_reset_, (int64_t)c, stream);
+  if (e != hipSuccess) return set_error(RDX_EHIP, std::string("reset launch: ") + hipGetErrorString(e));
   return RDX_OK;
 }
 

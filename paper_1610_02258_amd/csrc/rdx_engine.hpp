@@ -120,6 +120,9 @@ class Engine {
   // Counts for the run's current window index (host or device pointer).
   rdx_status upload_counts(Run* r, const int32_t* counts, bool device, hipStream_t stream);
   rdx_status reset_run(Run* r, hipStream_t stream);  // tallies, error flag, other buffer
+  // Every run to t = 0 with counts copied from device pointers src[j], all in
+  // one launch (the state the pair reset_run + upload_counts leaves).
+  rdx_status reset_runs_device(Run* const* runs, size_t n, const int32_t* const* src, hipStream_t stream);
   rdx_status download_counts(const Run* r, int32_t* out, bool device, hipStream_t stream);
 
   // Plans (Algorithm 1 schedule): windows up to t_end, at most max_windows
@@ -185,6 +188,12 @@ class Engine {
   int2* h_tile_map_ = nullptr;
   int32_t* h_n_tiles_ = nullptr;
   hipEvent_t staged_ = nullptr;
+  // batched reset: pinned chunk table, its device copy, and the event that
+  // marks the pinned table free again
+  ResetChunk* h_reset_ = nullptr;
+  ResetChunk* d_reset_ = nullptr;
+  size_t reset_cap_ = 0;
+  hipEvent_t reset_staged_ = nullptr;
   std::vector<const Run*> tile_runs_;  // runs of the tile map on the device
   std::vector<int64_t> tile_run_T_;
   int64_t k_now_ = 0;                  // batch step index == *d_base_

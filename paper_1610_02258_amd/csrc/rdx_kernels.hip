@@ -1167,6 +1167,19 @@ window_main_kernel(const StepArgs A) {
 }
 
 __global__ void advance_base_kernel(int32_t* base, int32_t add) { *base += add; }
+
+// Batched reset: one block per chunk.
+__global__ void __launch_bounds__(kBlock) reset_chunks_kernel(const ResetChunk* chunks) {
+  const ResetChunk c = chunks[blockIdx.x];
+  for (int64_t j = c.begin + threadIdx.x; j < c.end; j += kBlock) {
+    c.dst[j] = c.src[j];
+    c.other[j] = 0;
+  }
+  if (c.begin == 0) {
+    if (threadIdx.x < 2 * kTallySlots) c.tally[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *c.err = 0;
+  }
+}
 __global__ void set_base_kernel(int32_t* base, int32_t value) { *base = value; }
 
 // ----------------------------------------------------------- self-tests ----
@@ -1272,6 +1285,12 @@ hipError_t launch_advance_base(int32_t* base, int32_t add, hipStream_t stream) {
 
 hipError_t launch_set_base(int32_t* base, int32_t value, hipStream_t stream) {
   hipLaunchKernelGGL(set_base_kernel, dim3(1), dim3(1), 0, stream, base, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_chunks(const ResetChunk* chunks, int64_t n_chunks, hipStream_t stream) {
+  if (n_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reset_chunks_kernel, dim3((unsigned)n_chunks), dim3(kBlock), 0, stream, chunks);
   return hipGetLastError();
 }
 

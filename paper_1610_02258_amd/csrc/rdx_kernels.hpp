@@ -108,6 +108,20 @@ hipError_t launch_advance_base(int32_t* base, int32_t add, hipStream_t stream);
 // *base = value (one thread).
 hipError_t launch_set_base(int32_t* base, int32_t value, hipStream_t stream);
 
+// One chunk of a batched reset: elements [begin, end) of a run's counts are
+// copied from src to dst and cleared in other; the chunk with begin == 0 also
+// clears the run's tallies and error flag.
+struct ResetChunk {
+  const int32_t* src;
+  int32_t* dst;
+  int32_t* other;
+  unsigned long long* tally;  // [kTallySlots][2]
+  int32_t* err;
+  int64_t begin, end;
+};
+constexpr int64_t kResetChunk = 16384;  // elements per chunk
+hipError_t launch_reset_chunks(const ResetChunk* chunks, int64_t n_chunks, hipStream_t stream);
+
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s);
 hipError_t launch_copy(const int4* src, int4* dst, int64_t n16, hipStream_t s);

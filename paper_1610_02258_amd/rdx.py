@@ -55,6 +55,7 @@ SIGNATURES = {
     "rdx_batch_get_run_info": ([_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double)], C.c_int),
     "rdx_batch_set_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
     "rdx_batch_get_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
+    "rdx_batch_set_counts_all": ([_p, _p, _p], C.c_int),
     "rdx_batch_run": ([_p, _p, _p], C.c_int),
     "rdx_batch_step": ([_p, C.c_int64, _p], C.c_int),
     "rdx_batch_sync": ([_p, _p], C.c_int),
@@ -378,6 +379,14 @@ class Batch:
             c = np.ascontiguousarray(counts, np.int32).reshape(self.S, self.T[i])
             _check(lib().rdx_batch_set_counts(self._h, i, _np_ptr(c), 0, _stream_ptr(stream)),
                    "rdx_batch_set_counts")
+
+    def set_counts_all(self, counts, stream=None):
+        """Every run's counts from device tensors (one per run), in one launch."""
+        assert len(counts) == len(self.T)
+        for c, T in zip(counts, self.T):
+            assert _is_torch_cuda(c) and c.dtype.itemsize == 4 and c.is_contiguous() and c.numel() == self.S * T
+        ptrs = (C.c_void_p * len(counts))(*[c.data_ptr() for c in counts])
+        _check(lib().rdx_batch_set_counts_all(self._h, ptrs, _stream_ptr(stream)), "rdx_batch_set_counts_all")
 
     def get_counts(self, i: int, out=None, stream=None):
         if out is not None and _is_torch_cuda(out):

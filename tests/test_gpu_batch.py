@@ -168,6 +168,28 @@ def test_single_sim_with_graphs(rdx, oracle_lib):
         assert st.ssa_events == ref.tallies.ssa_events and st.moves == ref.tallies.moves
 
 
+def test_set_counts_all_in_one_launch(rdx, oracle_lib):
+    """Resetting every run from device tensors in one launch gives the same
+    results as the oracle, also when it restarts runs that already ran (the
+    count buffers then swap roles)."""
+    import torch
+    runs = _small_ensemble(n=5, seed=17)
+    _say(f"case: batched reset of {len(runs)} runs, T = {[w.mesh.n_tets for w in runs]}")
+    dev = [torch.from_numpy(np.ascontiguousarray(w.counts)).cuda() for w in runs]
+    b = _batch(rdx, runs)
+    b.set_exec_options(graph_windows=4)
+    t_end = [0.05 + 0.02 * i for i in range(len(runs))]
+    for rep in range(2):
+        refs = _refs(oracle_lib, runs)
+        b.set_counts_all(dev)
+        b.run(t_end)
+        for r, t in zip(refs, t_end):
+            r.run(t)
+        for i, r in enumerate(refs):
+            _assert_run(b, i, r, f"pass {rep}")
+        b.step(3)  # leave the runs at an odd window before the next reset
+
+
 def test_batch_structure_mismatch_is_rejected(rdx):
     a = I.ensemble_runs(n_runs=1, seed=1, t_lo=200, t_hi=300)[0]
     other = I.model_abc().as_dict()
