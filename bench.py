@@ -108,8 +108,13 @@ def batched_leg(steps: int = 2) -> dict:
         b.set_counts_all(c0, stream=stream)  # every run reset in one launch
         b.run(t_end, stream=stream)
 
-    batch_step()  # warm-up; also the online tuning of the launch shape
-    torch.cuda.synchronize()
+    # warm-up, which also runs the online tuning of the launch shape (its
+    # candidate shapes are timed on real windows; a step may not hold them all)
+    for _ in range(6):
+        batch_step()
+        torch.cuda.synchronize()
+        if not b.exec_options()["autotune"]:
+            break
     t0 = time.perf_counter()
     for _ in range(steps):
         batch_step()

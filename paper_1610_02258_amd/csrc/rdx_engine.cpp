@@ -575,7 +575,7 @@ void Engine::set_autotune(bool on) {
   if (!on) return;
   // the first entry is a warm-up of the default shape and is not scored
   candidates_ = {ExecShape{1, 1, 4}, ExecShape{1, 1, 4}, ExecShape{2, 1, 4}, ExecShape{1, 8, 4},
-                 ExecShape{2, 8, 4}, ExecShape{4, 8, 4}, ExecShape{1, 8, 1}, ExecShape{1, 8, 8}};
+                 ExecShape{2, 8, 4}, ExecShape{4, 8, 4}, ExecShape{1, 8, 8}};
 }
 
 rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
