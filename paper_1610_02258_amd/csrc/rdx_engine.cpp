@@ -540,7 +540,11 @@ rdx_status Engine::launch_plain(const StepArgs& a0, int64_t K, hipStream_t strea
 
 rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t stream) {
   const int W = shape_.graph_windows;
-  const auto key = std::make_pair(W, (a0.main_grid * 65536 + a0.detect_grid) * 16 + a0.ev_group_max);
+  // everything of the arguments that can change between sequences is in the
+  // key (pointers and tables are fixed for the engine's life)
+  const long long shape_key = ((long long)a0.main_grid << 40) | ((long long)a0.detect_grid << 8) |
+                              ((long long)a0.ev_group_max << 1) | (long long)a0.single_run;
+  const auto key = std::make_pair(W, shape_key);
   auto it = graphs_.find(key);
   if (it == graphs_.end()) {
     if (graphs_.size() >= 16) free_graphs();
@@ -615,6 +619,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
     int32_t pair_of[32];
     listing_pairs(model_host_, a.pairs, &a.n_pairs, pair_of);
   }
+  a.single_run = active.size() == 1 ? 1 : 0;
   a.wl_tile_count = wl_tile_count_;
   a.evq = evq_;
   a.evq_cap = (int32_t)((max_tiles_ + kQueues - 1) / kQueues);

@@ -200,7 +200,7 @@ class Engine {
 
   // graphs by (windows, grids); captured on a private stream
   hipStream_t capture_stream_ = nullptr;
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs_;
+  std::map<std::pair<int, long long>, hipGraphExec_t> graphs_;
 
   ExecShape shape_;
   bool tuning_ = false;

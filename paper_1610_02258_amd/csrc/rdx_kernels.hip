@@ -468,8 +468,9 @@ struct TileCtx {
 };
 
 __device__ __forceinline__ TileCtx tile_ctx(const StepArgs& A, int tile, int k) {
-  const int run = as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile];
-  const int first = as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile + 1];
+  // with one run the tile map is (0, 64 t): no load on the chain to the counts
+  const int run = A.single_run ? 0 : as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile];
+  const int first = A.single_run ? tile * kWave : as_const(reinterpret_cast<const int*>(A.tile_map))[2 * tile + 1];
   const cptr<RunDesc> rd = as_const(A.runs) + run;
   TileCtx c;
   c.rd = rd;
@@ -1090,7 +1091,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
     }
     if (lane < nq) {
       g_n = A.wl_tile_count[g_tile];
-      g_run = tile_run[2 * g_tile];
+      g_run = A.single_run ? 0 : tile_run[2 * g_tile];
     }
     // walk the group's tiles and their listed tets in order; the chunk is
     // run from one place in the code

@@ -67,6 +67,7 @@ struct StepArgs {
   int32_t detect_grid;         // persistent grid of the detect kernel
   int32_t main_grid;           // grid of the main kernel (event blocks + persistent diffusion blocks), >= 2
   int32_t ev_group_max;        // most queued tiles an event block packs into one chunk (1..8)
+  int32_t single_run;          // 1: one run, tile t is (run 0, first tet 64 t) without the tile map
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
   int32_t n_pairs;             // distinct reactant pairs of the second-order reactions
