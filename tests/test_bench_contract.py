@@ -1,0 +1,48 @@
+"""CPU checks of bench.py's contract: the one-GPU guard, the algorithmic byte
+counts the roofline divides by, and the hash gate on the committed HBM
+counter summary."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one GPU" in p.stderr
+
+
+def test_algorithmic_bytes_per_launch():
+    # main kernel: counts read + written (8 S), neighbours (16), couplings (32)
+    # per tet, plus 8 per moved molecule
+    assert bench.main_kernel_bytes(480_000, 10, 0.0) == 480_000 * 128
+    assert bench.main_kernel_bytes(1, 1, 3.0) == 56 + 24
+    # detect kernel: counts (4 S), N_A V (8), region label only with regions
+    assert bench.detect_kernel_bytes(480_000, 10, 1) == 480_000 * 48
+    assert bench.detect_kernel_bytes(10, 15, 2) == 10 * 69
+
+
+def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel text")
+    sha = hashlib.sha256(b"kernel text").hexdigest()
+    summary = tmp_path / "counters.txt"
+    summary.write_text("# comment: ignored\n"
+                       f"kernel_source_sha256: {sha}\n"
+                       "FETCH_SIZE_KiB_per_dispatch: 100\nWRITE_SIZE_KiB_per_dispatch: 50\n"
+                       "fetch_factor: 2.0\nwrite_factor: 1.0\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "COUNTERS", str(summary))
+    assert bench.measured_traffic() == pytest.approx((100 * 2.0 + 50) * 1024.0)
+    src.write_bytes(b"kernel text, changed")
+    assert bench.measured_traffic() is None
+
