@@ -217,3 +217,39 @@ def test_batch_options_validation(rdx):
     b.step(300)  # enough windows for every candidate
     o = b.exec_options()
     assert o["autotune"] == 0 and o["event_group"] in (4, 8) and o["fast_grid_div"] in (1, 2, 4)
+
+
+@pytest.mark.parametrize("S,R", [(16, 30), (12, 12)])
+def test_batch_random_models_with_regions(rdx, oracle_lib, S, R):
+    """Runs that share one random reaction structure (homodimers, sources,
+    immobile species) but differ in mesh, regions, rate constants, diffusion
+    coefficients and seed, with enough molecules that most tets list events:
+    the event chunks mix nothing across runs and every run equals the oracle
+    alone."""
+    from tests.randmodels import random_counts, random_model
+    rng = np.random.default_rng(700 + S + R)
+    base = random_model(rng, S, R, 2)
+    runs = []
+    for j, dims in enumerate([(3, 2, 2), (5, 4, 3), (2, 2, 7)]):
+        mesh = I.box_mesh(*dims, 0.5e-6, jitter=0.1, seed=40 + j)
+        mesh.region = rng.integers(0, 2, mesh.n_tets).astype(np.uint8)
+        md = dict(base)
+        md["kcst"] = base["kcst"] * rng.uniform(0.5, 1.5, base["kcst"].shape)
+        md["D"] = base["D"] * rng.uniform(0.5, 1.5, S)
+        counts = random_counts(rng, S, mesh.n_tets, mean=6.0)
+        runs.append((mesh, md, 300 + j, counts))
+    _say(f"case: batch of random S={S} R={R} models, T = {[m.n_tets for m, _, _, _ in runs]}")
+    b = rdx.Batch([(m.as_dict(), md, seed) for m, md, seed, _ in runs])
+    b.set_exec_options(graph_windows=2)
+    refs = []
+    for i, (m, md, seed, c) in enumerate(runs):
+        b.set_counts(i, c)
+        r = oracle_lib.Instance(m.as_dict(), md, seed)
+        r.reset(c)
+        refs.append(r)
+    for k in range(4):
+        b.step(1)
+        for r in refs:
+            r.step(1)
+        for i, r in enumerate(refs):
+            _assert_run(b, i, r, f"window {k}")
