@@ -120,3 +120,44 @@ def test_destroy_with_work_in_flight(rdx):
     t0 = time.time()
     srv.close()  # cancels the queued and running requests and joins the worker
     assert time.time() - t0 < 30.0
+
+
+def test_random_structure_requests_with_regions(rdx, oracle_lib):
+    """Requests sharing a random reaction structure (two regions, homodimers,
+    sources, immobile species) with per-request rates, diffusion
+    coefficients and meshes, more than the budget holds at once: each result
+    equals the oracle run alone."""
+    from tests.randmodels import random_counts, random_model
+    rng = np.random.default_rng(909)
+    S, R = 12, 12
+    base = random_model(rng, S, R, 2)
+    reqs = []
+    for j in range(8):
+        dims = tuple(int(v) for v in rng.integers(4, 11, 3))
+        mesh = I.box_mesh(*dims, 0.5e-6, jitter=0.1, seed=60 + j)
+        mesh.region = rng.integers(0, 2, mesh.n_tets).astype(np.uint8)
+        md = dict(base)
+        md["kcst"] = base["kcst"] * rng.uniform(0.5, 1.5, base["kcst"].shape)
+        md["D"] = base["D"] * rng.uniform(0.5, 1.5, S)
+        counts = random_counts(rng, S, mesh.n_tets, mean=4.0)
+        reqs.append((mesh, md, 500 + j, counts))
+    sizes = [m.n_tets for m, _, _, _ in reqs]
+    _say(f"case: server, random S={S} R={R} structure, T = {sizes}, 1 MiB budget")
+    srv = rdx.Server(base, hbm_budget_bytes=1 << 20, tick_windows=2)
+    t_end = []
+    tickets = []
+    for mesh, md, seed, counts in reqs:
+        ref = oracle_lib.Instance(mesh.as_dict(), md, seed)
+        t_end.append(4.5 * ref.tau)
+        tickets.append(srv.submit(mesh.as_dict(), md, seed, counts, t_end[-1]))
+    st = srv.stats()
+    assert sum(sizes) > st["capacity_tets"]
+    for (mesh, md, seed, counts), tk, te in zip(reqs, tickets, t_end):
+        got, info = srv.wait(tk, timeout_s=120.0)
+        ref = oracle_lib.Instance(mesh.as_dict(), md, seed)
+        ref.reset(counts)
+        ref.run(te)
+        np.testing.assert_array_equal(got, ref.counts)
+        assert info["stats"].ssa_events == ref.tallies.ssa_events
+        assert info["stats"].moves == ref.tallies.moves
+    srv.close()
