@@ -218,6 +218,66 @@ def serve_leg(n_requests: int = 400, rate: float = 200.0, submit_threads: int = 
             "submit_threads": submit_threads}
 
 
+SWEEP = [(0.1, 0.5), (1.0, 0.5), (10.0, 0.5), (1.0, 1.0), (1.0, 0.25)]
+
+
+def sweep_leg(steps: int, windows: int = 200) -> list:
+    """Density (0.1x, 1x, 10x molecules) and refinement (1, 0.5, 0.25 um
+    cubes) series of the simple-model box, each run for a fixed number of
+    windows: voxel-steps/s and SSA events/s on the graph path, then the two
+    kernels' average durations from a pass with HIP events."""
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for density, h in SWEEP:
+        w = inputs.config_simple_variant(density, h)
+        print(f"bench: sweep {w.name}", file=sys.stderr, flush=True)
+        sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+        t_end = windows * sim.tau
+        c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+
+        def run():
+            sim.set_counts(c0, stream=stream)
+            sim.run(t_end, stream=stream)
+
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = sim.stats(stream)
+        sim.kernel_times(reset=True)
+        sim.set_kernel_timing(True)
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        kt = sim.kernel_times(reset=True)
+        sim.set_kernel_timing(False)
+        n = max(kt["windows"], 1)
+        main_s, det_s = kt["main_ms"] * 1e-3 / n, kt["detect_ms"] * 1e-3 / n
+        b_main = main_kernel_bytes(sim.T, sim.S, st.moves / st.windows)
+        b_det = detect_kernel_bytes(sim.T, sim.S, w.model.kcst.shape[0])
+        rows.append({"workload": w.name, "n_tets": sim.T, "molecules": int(w.counts.sum()),
+                     "tau_s": sim.tau, "windows": st.windows,
+                     "voxel_steps_per_s": sim.T * st.windows * steps / el,
+                     "ssa_events_per_s": st.ssa_events * steps / el,
+                     "events_per_window": st.ssa_events / st.windows,
+                     "moves_per_s": st.moves * steps / el,
+                     "window_us": el * 1e6 / (st.windows * steps),
+                     "main_us": main_s * 1e6, "detect_us": det_s * 1e6,
+                     "main_frac_of_hbm": b_main / main_s / 1e9 / HBM_PEAK_GBS,
+                     "detect_frac_of_hbm": b_det / det_s / 1e9 / HBM_PEAK_GBS})
+        sim.close()
+        del c0
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +288,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline line, print the density and refinement series")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload is a single simulation on one "
@@ -241,6 +303,9 @@ def main() -> int:
     rdx.lib()  # fails loudly if the HIP library is missing
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_leg(max(args.steps // 4, 2))}), flush=True)
+        return 0
     w = inputs.config_simple()
     t0 = time.perf_counter()
     sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)

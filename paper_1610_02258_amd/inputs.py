@@ -435,6 +435,29 @@ def config_simple(seed: int = 1) -> Workload:
                     "480k tets, 10 species / 12 reactions, 1e6 molecules, 100 ms")
 
 
+def config_simple_variant(density: float = 1.0, h_um: float = 0.5, extent_um=(10.0, 10.0, 100.0),
+                          seed: int = 1, t_end: float = 100e-3) -> Workload:
+    """The simple-model workload with its molecule density and its mesh
+    resolution varied one at a time (the density and refinement series of
+    section 3.1, figures 3 and 4): a cuboid of ``extent_um`` cut into cubes
+    of edge ``h_um`` (6 tets each, 10% jitter), the same 10-species network,
+    and ``density`` x 100 molecules per cubic micrometre (1e6 in the full
+    10 x 10 x 100 um box), split among the species as in ``config_simple``."""
+    dims = tuple(max(1, int(round(e / h_um))) for e in extent_um)
+    mesh = box_mesh(*dims, h_um * UM, jitter=0.10, seed=seed)
+    model = model_simple10(seed)
+    rng = np.random.default_rng(seed + 100)
+    w = rng.uniform(0.5, 1.5, model.S)
+    total = int(round(density * 100.0 * float(np.prod([d * h_um for d in dims]))))
+    totals = np.floor(total * w / w.sum()).astype(np.int64)
+    totals[0] += total - int(totals.sum())
+    counts = place_uniform(mesh, totals, seed)
+    name = f"box{dims[0]}x{dims[1]}x{dims[2]}_h{h_um:g}um_simple10_density{density:g}x"
+    return Workload(name, mesh, model, counts, seed, t_end,
+                    f"{mesh.n_tets} tets of {h_um:g} um cubes, 10 species / 12 reactions, "
+                    f"{total} molecules ({density:g}x density)")
+
+
 def config_dendrite(seed: int = 2, target_tets: int = 1_000_000) -> Workload:
     """Random dendrite (~1e6 tets), calcium model, influx in 5% of tets, 50 ms."""
     mesh = dendrite_mesh(target_tets=target_tets, seed=seed)

@@ -238,3 +238,29 @@ def test_dendrite_full_size_prefix(rdx, oracle_lib):
         sim.step(1)
         ref.step(1)
         _assert_same(sim, ref, f"window {k}")
+
+
+@pytest.mark.parametrize("density,h,extent", [(10.0, 0.5, (3.0, 3.0, 4.0)), (0.1, 0.5, (3.0, 3.0, 4.0)),
+                                              (1.0, 0.25, (2.0, 2.0, 3.0)), (1.0, 1.0, (4.0, 4.0, 6.0))])
+def test_density_and_refinement_series(rdx, oracle_lib, density, h, extent):
+    """The simple-model recipe at 0.1x and 10x molecule density and at 0.25 and
+    1 um cubes, on boxes small enough for the oracle: every window compared."""
+    w = I.config_simple_variant(density, h, extent_um=extent)
+    _say(f"case: {w.name}, T={w.mesh.n_tets}, {int(w.counts.sum())} molecules")
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    for k in range(30):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
+
+
+def test_ten_times_density_full_size_prefix(rdx, oracle_lib):
+    """480,000 tets with 1e7 molecules (10x the benchmarked density): the
+    first windows compared on every count."""
+    w = I.config_simple_variant(10.0, 0.5)
+    _say(f"case: {w.name}, T={w.mesh.n_tets}")
+    sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    for k in range(2):
+        sim.step(1)
+        ref.step(1)
+        _assert_same(sim, ref, f"window {k}")
