@@ -56,6 +56,8 @@ def lib():
         L.os_destroy.restype = None
         L.os_get_tau.argtypes = [p]
         L.os_get_tau.restype = C.c_double
+        L.os_set_rates.argtypes = [p, p]
+        L.os_set_rates.restype = C.c_int
         L.os_get_geometry.argtypes = [p] * 9
         L.os_get_geometry.restype = None
         L.os_run.argtypes = [p, C.c_uint64, p, p, C.c_double, p, p]
@@ -188,6 +190,24 @@ class Instance:
     def set_counts(self, counts: np.ndarray):
         c = np.ascontiguousarray(counts, np.int32).reshape(self.S, self.T)
         self.counts = c.copy()
+
+    def set_rates(self, kcst: np.ndarray):
+        """Piecewise-constant forcing: new rate constants [n_regions, R] from
+        the next window on (the influx of section 3.2 changes every 1 ms)."""
+        kc = np.ascontiguousarray(kcst, np.float64).reshape(self.n_regions, self.R)
+        if lib().os_set_rates(self._h, _ptr(kc)) != OS_OK:
+            raise OracleError(-1, "set_rates: rate constants must be finite and >= 0")
+        self.kcst = kc.copy()
+
+    def region_counts(self) -> np.ndarray:
+        """Recording (section 3.2 records per-region counts every 0.02 ms): the
+        molecules of each species summed over the tets of each region, as
+        int64 [n_regions, S], straight from the definition."""
+        reg = np.zeros(self.T, np.int64) if self.region is None else self.region.astype(np.int64)
+        out = np.zeros((self.n_regions, self.S), np.int64)
+        for g in range(self.n_regions):
+            out[g] = self.counts[:, reg == g].astype(np.int64).sum(axis=1)
+        return out
 
     def reset(self, counts: np.ndarray, seed: int | None = None):
         """New realisation: counts at t = 0, window 0, optionally a new seed."""

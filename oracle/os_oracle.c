@@ -17,6 +17,8 @@
  *                   in proportion to the face diffusion rates;
  *     apply all moves.
  * The window length is tau = min over (S, tet) of 1/d_{S,tet} (section 2.1).
+ * Between windows the rate constants may be replaced (os_set_rates), the
+ * piecewise-constant forcing of section 3.2.
  *
  * Readings of points the paper leaves open (each is listed in the design doc):
  *   - occupancy is finalised at the window end, O_S += N_S (tau - t_S), and a
@@ -487,6 +489,20 @@ int os_build(int32_t n_verts, const double* verts, int32_t T, const int32_t* tet
 }
 
 double os_get_tau(const os_instance* I) { return I->tau; }
+
+/* Time-varying forcing: replace the [n_regions*R] rate constants between
+ * windows (a piecewise-constant influx such as the calcium influx of section
+ * 3.2 is a zero-order reaction whose constant changes over time).  The next
+ * window uses the new constants; the window length tau depends only on the
+ * diffusion coefficients and stays as it is. */
+int os_set_rates(os_instance* I, const double* kcst)
+{
+  size_t n = (size_t)I->n_regions * (size_t)I->R;
+  for (size_t i = 0; i < n; ++i)
+    if (!(kcst[i] >= 0.0) || !isfinite(kcst[i])) return OS_EINVAL;
+  memcpy(I->kcst, kcst, sizeof(double) * n);
+  return OS_OK;
+}
 
 /* Export the derived geometry for tests (arrays sized as in os_instance). */
 void os_get_geometry(const os_instance* I, int32_t* nbr, double* vol, double* area,
