@@ -134,6 +134,30 @@ rdx_status rdx_sync(rdx_sim* sim, void* stream);
 /* Synchronises `stream` and returns the tallies, t and window index. */
 rdx_status rdx_get_stats(rdx_sim* sim, rdx_stats* stats, void* stream);
 
+/* Time-varying forcing (section 3.2: the calcium influx, a zero-order
+ * reaction, changes every 1 ms).  Replaces the rate constants kcst
+ * [n_regions*n_reactions] (host pointer, region-major as in rdx_model,
+ * n = n_regions*n_reactions) for every window enqueued on `stream` after
+ * this call; windows enqueued before it keep the old constants.  To switch
+ * at a time t_s, run to t_s first (the window that crosses t_s is cut there,
+ * as at any t_end).  Synchronises `stream` before it returns, so kcst may be
+ * freed at once.  tau does not change (it depends on diffusion only).  The
+ * table is not part of a checkpoint (rdx_save): set it again after rdx_load.
+ * Errors: RDX_EINVAL (null handle, null kcst with n > 0, wrong n, a negative
+ * or non-finite constant; the old table stays), RDX_EHIP. */
+rdx_status rdx_set_rate_constants(rdx_sim* sim, const double* kcst, int64_t n, void* stream);
+
+/* Recording (section 3.2 records per-region counts every 0.02 ms): out
+ * [n_regions*n_species] int64, region-major, the molecules of each species
+ * summed over the tets of each region, for the counts after all windows
+ * enqueued so far on `stream`.  With is_device_ptr the sums are written by
+ * kernels on `stream` and the call returns at once, so that a caller fills
+ * a device ring buffer (one slot of n_regions*n_species per record) with no
+ * host synchronisation between windows; the caller owns out and keeps it
+ * alive until `stream` reaches the call.  With a host pointer the call waits.
+ * Errors: RDX_EINVAL (null), RDX_EHIP. */
+rdx_status rdx_region_counts(rdx_sim* sim, int64_t* out, int is_device_ptr, void* stream);
+
 rdx_status rdx_get_tau(const rdx_sim* sim, double* tau);
 rdx_status rdx_get_sizes(const rdx_sim* sim, int32_t* n_tets, int32_t* n_species,
                          int32_t* n_reactions);
@@ -226,6 +250,12 @@ rdx_status rdx_batch_set_counts(rdx_batch* batch, int32_t i, const int32_t* coun
                                 void* stream);
 rdx_status rdx_batch_get_counts(rdx_batch* batch, int32_t i, int32_t* out, int is_device_ptr,
                                 void* stream);
+/* As rdx_set_rate_constants / rdx_region_counts for run i (each run has its
+ * own rate table). */
+rdx_status rdx_batch_set_rate_constants(rdx_batch* batch, int32_t i, const double* kcst, int64_t n,
+                                        void* stream);
+rdx_status rdx_batch_region_counts(rdx_batch* batch, int32_t i, int64_t* out, int is_device_ptr,
+                                   void* stream);
 /* rdx_batch_set_counts for every run at once, from device memory, in one
  * launch: counts[i] is a device pointer to run i's [n_species*n_tets] int32
  * counts (caller-owned, alive until `stream` reaches the call); the host
@@ -327,7 +357,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 202
+#define RDX_ABI_VERSION 203
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

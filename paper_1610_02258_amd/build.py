@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librdx.so")
-SOURCES = ["rdx_setup.cpp", "rdx_engine.cpp", "rdx_api.cpp", "rdx_server.cpp", "rdx_kernels.hip"]
+SOURCES = ["rdx_setup.cpp", "rdx_engine.cpp", "rdx_api.cpp", "rdx_server.cpp", "rdx_kernels.hip", "rdx_record.hip"]
 ARCH = os.environ.get("RDX_OFFLOAD_ARCH", "gfx950")
 
 

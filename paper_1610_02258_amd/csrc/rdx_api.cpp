@@ -36,6 +36,7 @@ struct rdx_sim {
   Engine eng;
   Run run;
   int device = 0;
+  unsigned long long* rec = nullptr;  // device staging of region sums for host output
 };
 
 // A batch: one engine holding every run; all runs advance in the same launches.
@@ -43,6 +44,7 @@ struct rdx_batch {
   Engine eng;
   std::vector<Run> runs;
   int device = 0;
+  unsigned long long* rec = nullptr;
 };
 
 namespace {
@@ -56,6 +58,29 @@ namespace {
 
 rdx_status check_sim(const rdx_sim* s) {
   if (!s) return set_error(RDX_EINVAL, "null simulation handle");
+  return RDX_OK;
+}
+
+rdx_status set_rates_of(Engine& eng, Run& r, const double* kcst, int64_t n, hipStream_t stream) {
+  const int64_t want = (int64_t)r.host.n_regions * (int64_t)r.host.R;
+  if (n != want)
+    return set_error(RDX_EINVAL, "the rate table has n_regions*n_reactions = " + std::to_string(want) +
+                                     " entries, got " + std::to_string(n));
+  if (want == 0) return RDX_OK;
+  if (!kcst) return set_error(RDX_EINVAL, "null rate constants");
+  return eng.set_rates(&r, kcst, stream);
+}
+
+rdx_status region_counts_of(Engine& eng, const Run& r, int64_t* out, bool device, unsigned long long** rec,
+                            hipStream_t stream) {
+  if (!out) return set_error(RDX_EINVAL, "null output");
+  if (device) return eng.region_counts(&r, reinterpret_cast<unsigned long long*>(out), stream);
+  if (!*rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(rec), sizeof(unsigned long long) * kMaxRegions * kMaxSpecies));
+  const rdx_status q = eng.region_counts(&r, *rec, stream);
+  if (q != RDX_OK) return q;
+  const size_t n = (size_t)r.host.n_regions * (size_t)r.host.S;
+  RDX_HIP(hipMemcpyAsync(out, *rec, sizeof(int64_t) * n, hipMemcpyDeviceToHost, stream));
+  RDX_HIP(hipStreamSynchronize(stream));
   return RDX_OK;
 }
 
@@ -149,7 +174,22 @@ void rdx_destroy(rdx_sim* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
   (void)hipDeviceSynchronize();
+  if (s->rec) (void)hipFree(s->rec);
   delete s;
+}
+
+rdx_status rdx_set_rate_constants(rdx_sim* s, const double* kcst, int64_t n, void* stream) {
+  clear_error();
+  if (check_sim(s) != RDX_OK) return RDX_EINVAL;
+  (void)hipSetDevice(s->device);
+  return set_rates_of(s->eng, s->run, kcst, n, reinterpret_cast<hipStream_t>(stream));
+}
+
+rdx_status rdx_region_counts(rdx_sim* s, int64_t* out, int is_device_ptr, void* stream) {
+  clear_error();
+  if (check_sim(s) != RDX_OK) return RDX_EINVAL;
+  (void)hipSetDevice(s->device);
+  return region_counts_of(s->eng, s->run, out, is_device_ptr != 0, &s->rec, reinterpret_cast<hipStream_t>(stream));
 }
 
 rdx_status rdx_set_counts(rdx_sim* s, const int32_t* counts, int is_device_ptr, void* stream) {
@@ -400,6 +440,7 @@ void rdx_batch_destroy(rdx_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
+  if (b->rec) (void)hipFree(b->rec);
   delete b;
 }
 
@@ -407,6 +448,21 @@ static rdx_status check_batch_run(const rdx_batch* b, int32_t i) {
   if (!b) return set_error(RDX_EINVAL, "null batch handle");
   if (i < 0 || (size_t)i >= b->runs.size()) return set_error(RDX_EINVAL, "run index out of range");
   return RDX_OK;
+}
+
+rdx_status rdx_batch_set_rate_constants(rdx_batch* b, int32_t i, const double* kcst, int64_t n, void* stream) {
+  clear_error();
+  if (check_batch_run(b, i) != RDX_OK) return RDX_EINVAL;
+  (void)hipSetDevice(b->device);
+  return set_rates_of(b->eng, b->runs[(size_t)i], kcst, n, reinterpret_cast<hipStream_t>(stream));
+}
+
+rdx_status rdx_batch_region_counts(rdx_batch* b, int32_t i, int64_t* out, int is_device_ptr, void* stream) {
+  clear_error();
+  if (check_batch_run(b, i) != RDX_OK) return RDX_EINVAL;
+  (void)hipSetDevice(b->device);
+  return region_counts_of(b->eng, b->runs[(size_t)i], out, is_device_ptr != 0, &b->rec,
+                          reinterpret_cast<hipStream_t>(stream));
 }
 
 rdx_status rdx_batch_size(const rdx_batch* b, int32_t* n_runs) {

@@ -126,6 +126,17 @@ void listing_coefficients(const DevModel& m, const double* k, double* out) {
   }
 }
 
+// Device image of a run's rate table: [kMaxRegions][32] constants, then
+// [kMaxRegions][kLStride] listing coefficients, zero-padded.
+static std::vector<double> rate_image(const DevModel& m, const HostInstance& I) {
+  std::vector<double> kc((size_t)kMaxRegions * (32 + kLStride), 0.0);
+  for (int reg = 0; reg < I.n_regions; ++reg) {
+    for (int q = 0; q < I.R; ++q) kc[(size_t)reg * 32 + q] = I.kcst[(size_t)reg * I.R + q];
+    listing_coefficients(m, &I.kcst[(size_t)reg * I.R], &kc[(size_t)kMaxRegions * 32 + (size_t)reg * kLStride]);
+  }
+  return kc;
+}
+
 DevModel make_dev_model(const HostInstance& I) {
   DevModel m;
   std::memset(&m, 0, sizeof m);
@@ -291,11 +302,7 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
     geo[4 * i + 2] = I.cum[4 * i + 1];
     geo[4 * i + 3] = I.cum[4 * i + 2];
   }
-  std::vector<double> kc((size_t)kMaxRegions * (32 + kLStride), 0.0);
-  for (int reg = 0; reg < I.n_regions; ++reg) {
-    for (int q = 0; q < I.R; ++q) kc[(size_t)reg * 32 + q] = I.kcst[(size_t)reg * I.R + q];
-    listing_coefficients(model_host_, &I.kcst[(size_t)reg * I.R], &kc[(size_t)kMaxRegions * 32 + (size_t)reg * kLStride]);
-  }
+  const std::vector<double> kc = rate_image(model_host_, I);
   hipError_t e = hipMemcpyAsync(r->nbr, I.nbr.data(), 16 * T, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->geo, geo.data(), 32 * T, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipMemcpyAsync(r->nav, I.nav.data(), 8 * T, hipMemcpyHostToDevice, stream);
@@ -385,6 +392,27 @@ rdx_status Engine::upload_counts(Run* r, const int32_t* counts, bool device, hip
   RDX_HIP(hipMemcpyAsync(r->cnt[r->window & 1], counts, sizeof(int32_t) * n,
                          device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream));
   if (!device) RDX_HIP(hipStreamSynchronize(stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::set_rates(Run* r, const double* kcst, hipStream_t stream) {
+  const size_t n = (size_t)r->host.n_regions * (size_t)r->host.R;
+  for (size_t i = 0; i < n; ++i)
+    if (!(kcst[i] >= 0.0) || !std::isfinite(kcst[i]))
+      return set_error(RDX_EINVAL, "rate constants must be finite and >= 0");
+  r->host.kcst.assign(kcst, kcst + n);
+  const std::vector<double> kc = rate_image(model_host_, r->host);
+  // stream-ordered: windows already enqueued keep the old constants; the
+  // captured window graphs read the table through its pointer and need no
+  // re-capture
+  RDX_HIP(hipMemcpyAsync(r->kcst, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, stream));
+  RDX_HIP(hipStreamSynchronize(stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::region_counts(const Run* r, unsigned long long* out, hipStream_t stream) {
+  RDX_HIP(launch_region_counts(r->cnt[r->window & 1], r->region, r->host.T, r->host.S, r->host.n_regions,
+                               out, stream));
   return RDX_OK;
 }
 

@@ -124,6 +124,12 @@ class Engine {
   // one launch (the state the pair reset_run + upload_counts leaves).
   rdx_status reset_runs_device(Run* const* runs, size_t n, const int32_t* const* src, hipStream_t stream);
   rdx_status download_counts(const Run* r, int32_t* out, bool device, hipStream_t stream);
+  // Time-varying forcing: new rate constants [n_regions*R] for the windows
+  // enqueued after this call on `stream` (waits for the upload).
+  rdx_status set_rates(Run* r, const double* kcst, hipStream_t stream);
+  // Recording: per-region sums of the current counts into the device array
+  // out [n_regions*S], enqueued on `stream`.
+  rdx_status region_counts(const Run* r, unsigned long long* out, hipStream_t stream);
 
   // Plans (Algorithm 1 schedule): windows up to t_end, at most max_windows
   // (< 0: no limit); or n full windows.

@@ -28,6 +28,10 @@ SIGNATURES = {
     "rdx_destroy": ([_p], None),
     "rdx_set_counts": ([_p, _p, C.c_int, _p], C.c_int),
     "rdx_get_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_set_rate_constants": ([_p, _p, C.c_int64, _p], C.c_int),
+    "rdx_region_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_batch_set_rate_constants": ([_p, C.c_int32, _p, C.c_int64, _p], C.c_int),
+    "rdx_batch_region_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
     "rdx_run": ([_p, C.c_double, _p], C.c_int),
     "rdx_step": ([_p, C.c_int64, _p], C.c_int),
     "rdx_sync": ([_p, _p], C.c_int),
@@ -233,6 +237,7 @@ class Sim:
                             C.byref(h)), "rdx_create")
         self._h = h
         self.T, self.S, self.R = T, S, R
+        self.n_regions = int(md.n_regions)
         tau = C.c_double()
         _check(L.rdx_get_tau(h, C.byref(tau)), "rdx_get_tau")
         self.tau = tau.value
@@ -266,6 +271,24 @@ class Sim:
             return out
         c = np.zeros((self.S, self.T), np.int32)
         _check(lib().rdx_get_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_get_counts")
+        return c
+
+    def set_rate_constants(self, kcst, stream=None):
+        """Rate constants [n_regions, R] for the windows enqueued after this
+        call (piecewise-constant forcing); waits for `stream`."""
+        k = np.ascontiguousarray(kcst, np.float64).reshape(-1)
+        _check(lib().rdx_set_rate_constants(self._h, _np_ptr(k), k.size, _stream_ptr(stream)),
+               "rdx_set_rate_constants")
+
+    def region_counts(self, out=None, stream=None):
+        """Per-region molecule sums, int64 [n_regions, S].  With `out` a CUDA
+        int64 tensor (e.g. one slot of a recording ring) the sums are written
+        on `stream` without waiting."""
+        if out is not None and _is_torch_cuda(out):
+            _check(lib().rdx_region_counts(self._h, out.data_ptr(), 1, _stream_ptr(stream)), "rdx_region_counts")
+            return out
+        c = np.zeros((self.n_regions, self.S), np.int64)
+        _check(lib().rdx_region_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_region_counts")
         return c
 
     def run(self, t_end: float, stream=None):
@@ -338,6 +361,7 @@ class Batch:
         taus = (C.c_double * n)()
         self._keep = []
         self.T, self.S, self.R = [], None, None
+        self.n_regions = []
         for i, r in enumerate(runs):
             mesh, model, seed = r[0], r[1], r[2]
             m, md, keep, T, S, R = _marshal(mesh, model)
@@ -346,6 +370,7 @@ class Batch:
             taus[i] = float(r[3]) if len(r) > 3 else 0.0
             self._keep.append(keep)
             self.T.append(T)
+            self.n_regions.append(int(md.n_regions))
             self.S, self.R = S, R
         h = C.c_void_p()
         _check(L.rdx_batch_create(n, meshes, models, seeds, taus, C.byref(h)), "rdx_batch_create")
@@ -395,6 +420,21 @@ class Batch:
             return out
         c = np.zeros((self.S, self.T[i]), np.int32)
         _check(lib().rdx_batch_get_counts(self._h, i, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_batch_get_counts")
+        return c
+
+    def set_rate_constants(self, i: int, kcst, stream=None):
+        k = np.ascontiguousarray(kcst, np.float64).reshape(-1)
+        _check(lib().rdx_batch_set_rate_constants(self._h, i, _np_ptr(k), k.size, _stream_ptr(stream)),
+               "rdx_batch_set_rate_constants")
+
+    def region_counts(self, i: int, out=None, stream=None):
+        if out is not None and _is_torch_cuda(out):
+            _check(lib().rdx_batch_region_counts(self._h, i, out.data_ptr(), 1, _stream_ptr(stream)),
+                   "rdx_batch_region_counts")
+            return out
+        c = np.zeros((self.n_regions[i], self.S), np.int64)
+        _check(lib().rdx_batch_region_counts(self._h, i, _np_ptr(c), 0, _stream_ptr(stream)),
+               "rdx_batch_region_counts")
         return c
 
     def run(self, t_end, stream=None):
