@@ -278,6 +278,126 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
     return rows
 
 
+def record_kernel_bytes(T: int, S: int, n_regions: int) -> float:
+    """Bytes the per-region count reduction must read: the counts (4 S per
+    tet) and, with regions, the region labels (1 per tet)."""
+    return float(T) * (4 * S + (1 if n_regions > 1 else 0))
+
+
+def forcing_leg(sim_ms: float = 2.0, record_ms: float = 0.02, force_ms: float = 1.0) -> dict:
+    """Time-varying forcing and recording as section 3.2 uses them, on the
+    dendrite workload: the calcium influx redrawn every `force_ms` (x U(0.5,
+    3)), per-region counts recorded every `record_ms` into a device ring
+    (run to the record time, then the reduction writes the ring slot; no
+    host sync), against the plain run of the same span.  Then the simple
+    model recorded after every window against its graph path, and the
+    reduction kernel alone, timed back to back with events on its stream."""
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    w = inputs.config_dendrite()
+    md = w.model.as_dict()
+    sim = rdx.Sim(w.mesh.as_dict(), md, w.seed)
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+    t_end = sim_ms * 1e-3
+    n_rec = int(round(sim_ms / record_ms))
+    per_force = int(round(force_ms / record_ms))
+    ring = torch.zeros((n_rec, sim.n_regions, sim.S), dtype=torch.int64, device=dev)
+    influx = np.flatnonzero(np.asarray(md["lhs"]).sum(axis=1) == 0)
+    rng = np.random.default_rng(12)
+    tables = []
+    for _ in range((n_rec + per_force - 1) // per_force):
+        k = np.array(md["kcst"], np.float64)
+        k[:, influx] *= rng.uniform(0.5, 3.0)
+        tables.append(k)
+
+    def plain():
+        sim.set_rate_constants(md["kcst"], stream=stream)
+        sim.set_counts(c0, stream=stream)
+        sim.run(t_end, stream=stream)
+
+    def forced():
+        sim.set_counts(c0, stream=stream)
+        for r in range(n_rec):
+            if r % per_force == 0:
+                sim.set_rate_constants(tables[r // per_force], stream=stream)
+            sim.run((r + 1) * record_ms * 1e-3, stream=stream)
+            sim.region_counts(out=ring[r], stream=stream)
+
+    res = {}
+    for name, fn in (("plain", plain), ("forced_recorded", forced)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = sim.stats(stream)
+        res[name] = {"s": el, "windows": st.windows, "voxel_steps_per_s": st.voxel_steps / el,
+                     "ssa_events_per_s": st.ssa_events / el}
+    out["dendrite"] = {"workload": w.name, "n_tets": sim.T, "species": sim.S, "regions": sim.n_regions,
+                       "tau_s": sim.tau, "simulated_s": t_end, "records": n_rec,
+                       "rate_updates": len(tables), **{k: v for k, v in res.items()},
+                       "overhead": res["forced_recorded"]["s"] / res["plain"]["s"] - 1.0}
+    # the reduction alone at this size
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 200
+    ev0.record(stream)
+    for r in range(reps):
+        sim.region_counts(out=ring[r % n_rec], stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    b = record_kernel_bytes(sim.T, sim.S, sim.n_regions)
+    out["record_kernel_dendrite"] = {"avg_us": us, "bytes": b, "GBs": b / us / 1e3,
+                                     "frac_of_hbm": b / us / 1e3 / HBM_PEAK_GBS}
+    sim.close()
+    del c0, ring
+
+    w = inputs.config_simple()
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+    n_win = 220
+    ring = torch.zeros((n_win, sim.n_regions, sim.S), dtype=torch.int64, device=dev)
+
+    def every_window():
+        sim.set_counts(c0, stream=stream)
+        for r in range(n_win):
+            sim.step(1, stream=stream)
+            sim.region_counts(out=ring[r], stream=stream)
+
+    def graph_path():
+        sim.set_counts(c0, stream=stream)
+        sim.step(n_win, stream=stream)
+
+    res = {}
+    for name, fn in (("graph_path", graph_path), ("recorded_every_window", every_window)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / 3
+        res[name] = {"window_us": el * 1e6 / n_win, "voxel_steps_per_s": sim.T * n_win / el}
+    ev0.record(stream)
+    for r in range(reps):
+        sim.region_counts(out=ring[r % n_win], stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) * 1e3 / reps
+    b = record_kernel_bytes(sim.T, sim.S, sim.n_regions)
+    out["simple"] = {"workload": w.name, "windows": n_win, **res}
+    out["record_kernel_simple"] = {"avg_us": us, "bytes": b, "GBs": b / us / 1e3,
+                                   "frac_of_hbm": b / us / 1e3 / HBM_PEAK_GBS}
+    sim.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,6 +410,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print the density and refinement series")
+    ap.add_argument("--forcing", action="store_true",
+                    help="instead of the headline line, print the forcing and recording measurements")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload is a single simulation on one "
@@ -305,6 +427,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     if args.sweep:
         print(json.dumps({"sweep": sweep_leg(max(args.steps // 4, 2))}), flush=True)
+        return 0
+    if args.forcing:
+        print(json.dumps({"forcing": forcing_leg()}), flush=True)
         return 0
     w = inputs.config_simple()
     t0 = time.perf_counter()

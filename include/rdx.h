@@ -155,6 +155,9 @@ rdx_status rdx_set_rate_constants(rdx_sim* sim, const double* kcst, int64_t n, v
  * a device ring buffer (one slot of n_regions*n_species per record) with no
  * host synchronisation between windows; the caller owns out and keeps it
  * alive until `stream` reaches the call.  With a host pointer the call waits.
+ * The first call allocates a 257 KB device buffer for partial sums, kept
+ * until rdx_destroy; calls on one handle share it, so order them on one
+ * stream.
  * Errors: RDX_EINVAL (null), RDX_EHIP. */
 rdx_status rdx_region_counts(rdx_sim* sim, int64_t* out, int is_device_ptr, void* stream);
 

@@ -74,12 +74,16 @@ rdx_status set_rates_of(Engine& eng, Run& r, const double* kcst, int64_t n, hipS
 rdx_status region_counts_of(Engine& eng, const Run& r, int64_t* out, bool device, unsigned long long** rec,
                             hipStream_t stream) {
   if (!out) return set_error(RDX_EINVAL, "null output");
-  if (device) return eng.region_counts(&r, reinterpret_cast<unsigned long long*>(out), stream);
-  if (!*rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(rec), sizeof(unsigned long long) * kMaxRegions * kMaxSpecies));
-  const rdx_status q = eng.region_counts(&r, *rec, stream);
+  // one device buffer per handle, made at the first call: the partial sums,
+  // then a staging copy of the result for host output
+  constexpr size_t kStage = sizeof(unsigned long long) * kMaxRegions * kMaxSpecies;
+  if (!*rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(rec), kRegionScratchBytes + kStage));
+  unsigned long long* stage = *rec + kRegionScratchBytes / sizeof(unsigned long long);
+  if (device) return eng.region_counts(&r, *rec, reinterpret_cast<unsigned long long*>(out), stream);
+  const rdx_status q = eng.region_counts(&r, *rec, stage, stream);
   if (q != RDX_OK) return q;
   const size_t n = (size_t)r.host.n_regions * (size_t)r.host.S;
-  RDX_HIP(hipMemcpyAsync(out, *rec, sizeof(int64_t) * n, hipMemcpyDeviceToHost, stream));
+  RDX_HIP(hipMemcpyAsync(out, stage, sizeof(int64_t) * n, hipMemcpyDeviceToHost, stream));
   RDX_HIP(hipStreamSynchronize(stream));
   return RDX_OK;
 }

@@ -410,9 +410,10 @@ rdx_status Engine::set_rates(Run* r, const double* kcst, hipStream_t stream) {
   return RDX_OK;
 }
 
-rdx_status Engine::region_counts(const Run* r, unsigned long long* out, hipStream_t stream) {
+rdx_status Engine::region_counts(const Run* r, unsigned long long* scratch, unsigned long long* out,
+                                 hipStream_t stream) {
   RDX_HIP(launch_region_counts(r->cnt[r->window & 1], r->region, r->host.T, r->host.S, r->host.n_regions,
-                               out, stream));
+                               scratch, out, stream));
   return RDX_OK;
 }
 

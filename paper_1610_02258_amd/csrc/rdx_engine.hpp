@@ -128,8 +128,9 @@ class Engine {
   // enqueued after this call on `stream` (waits for the upload).
   rdx_status set_rates(Run* r, const double* kcst, hipStream_t stream);
   // Recording: per-region sums of the current counts into the device array
-  // out [n_regions*S], enqueued on `stream`.
-  rdx_status region_counts(const Run* r, unsigned long long* out, hipStream_t stream);
+  // out [n_regions*S], enqueued on `stream`; scratch holds kRegionScratchBytes.
+  rdx_status region_counts(const Run* r, unsigned long long* scratch, unsigned long long* out,
+                           hipStream_t stream);
 
   // Plans (Algorithm 1 schedule): windows up to t_end, at most max_windows
   // (< 0: no limit); or n full windows.

@@ -124,9 +124,13 @@ constexpr int64_t kResetChunk = 16384;  // elements per chunk
 hipError_t launch_reset_chunks(const ResetChunk* chunks, int64_t n_chunks, hipStream_t stream);
 
 // Recording (rdx_record.hip): out [n_regions * S] = per-region sums of the
-// counts [S][T]; region may be null when n_regions == 1.  Zeroes out first.
+// counts [S][T]; region may be null when n_regions == 1.  scratch is a device
+// array of kRegionScratchBytes for per-block partial sums (calls sharing it
+// must be ordered on one stream).
+constexpr size_t kRegionScratchBytes = 4096 * 8 * 8;
 hipError_t launch_region_counts(const int32_t* counts, const uint8_t* region, int32_t T, int32_t S,
-                                int32_t n_regions, unsigned long long* out, hipStream_t stream);
+                                int32_t n_regions, unsigned long long* scratch, unsigned long long* out,
+                                hipStream_t stream);
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s);

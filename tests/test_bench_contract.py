@@ -31,6 +31,12 @@ def test_algorithmic_bytes_per_launch():
     assert bench.detect_kernel_bytes(10, 15, 2) == 10 * 69
 
 
+def test_record_kernel_bytes():
+    # counts (4 S per tet), plus the region label only with regions
+    assert bench.record_kernel_bytes(996_564, 15, 2) == 996_564 * 61
+    assert bench.record_kernel_bytes(480_000, 10, 1) == 480_000 * 40
+
+
 def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
     src.write_bytes(b"kernel text")

@@ -174,3 +174,31 @@ def test_dendrite_influx_switch_full_size(rdx, oracle_lib):
         ref.step(1)
         _same(sim, ref, f"influx x{scale}")
     sim.close()
+
+
+@pytest.mark.parametrize("dims,n_regions", [((10, 9, 7), 8), ((7, 6, 5), 5), ((1, 1, 1), 2), ((9, 9, 9), 1)])
+def test_region_counts_sizes_and_wide_sums(rdx, oracle_lib, dims, n_regions):
+    """Region sums straight after set_counts with counts up to 2^30 - 1, so
+    sums pass 2^32: 8 and 5 regions (the widest accumulator variant), a
+    6-tet mesh smaller than one block, one region; host and device output."""
+    import torch
+    rng = np.random.default_rng(sum(dims) + n_regions)
+    S = 16 if n_regions == 8 else 3
+    mesh = I.box_mesh(*dims, 0.5e-6, seed=5)
+    mesh.region = rng.integers(0, n_regions, mesh.n_tets).astype(np.uint8)
+    mesh.region[:n_regions] = np.arange(min(n_regions, mesh.n_tets))
+    md = random_model(rng, S, 4, n_regions)
+    counts = rng.integers(0, 2**30, (S, mesh.n_tets)).astype(np.int32)
+    _say(f"case: region sums, T={mesh.n_tets} S={S} regions={n_regions}")
+    sim = rdx.Sim(mesh.as_dict(), md, 1)
+    ref = oracle_lib.Instance(mesh.as_dict(), md, 1)
+    sim.set_counts(counts)
+    ref.set_counts(counts)
+    want = ref.region_counts()
+    if mesh.n_tets > 100:
+        assert want.max() > 2**32
+    assert np.array_equal(sim.region_counts(), want)
+    dev = torch.full((n_regions, S), -7, dtype=torch.int64, device="cuda:0")
+    sim.region_counts(out=dev)
+    assert np.array_equal(dev.cpu().numpy(), want)
+    sim.close()
