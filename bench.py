@@ -14,6 +14,11 @@ of the main window kernel (algorithmic bytes per launch over its average
 launch time from HIP events on the launch stream, taken over a second pass of
 the same steps with per-kernel events), and the oracle timed on host cores on
 a bounded sample of the same workload.
+
+Two other modes print their own line instead: ``--sweep`` (the density and
+refinement series of the same box) and ``--forcing`` (time-varying influx and
+per-region recording on the dendrite workload, and the recording kernel's
+bandwidth).
 """
 from __future__ import annotations
 
