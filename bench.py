@@ -379,8 +379,13 @@ def forcing_leg(sim_ms: float = 2.0, record_ms: float = 0.02, force_ms: float = 
         sim.set_counts(c0, stream=stream)
         sim.step(n_win, stream=stream)
 
+    def every_window_native():  # the same records, looped inside the library
+        sim.set_counts(c0, stream=stream)
+        sim.step_recorded(n_win, 1, ring, stream=stream)
+
     res = {}
-    for name, fn in (("graph_path", graph_path), ("recorded_every_window", every_window)):
+    for name, fn in (("graph_path", graph_path), ("recorded_every_window", every_window),
+                     ("recorded_every_window_native", every_window_native)):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -161,6 +161,19 @@ rdx_status rdx_set_rate_constants(rdx_sim* sim, const double* kcst, int64_t n, v
  * Errors: RDX_EINVAL (null), RDX_EHIP. */
 rdx_status rdx_region_counts(rdx_sim* sim, int64_t* out, int is_device_ptr, void* stream);
 
+/* Recording at a fixed window interval (section 3.2 records every 0.02 ms):
+ * n_windows full windows of tau, and after each `every` of them the
+ * per-region sums (as rdx_region_counts) into slot j mod ring_slots of the
+ * device ring [ring_slots][n_regions*n_species] int64, for records j = 0, 1,
+ * ... of this call (a trailing group shorter than `every` is not recorded).
+ * The loop runs in the library, so the records cost no host round trip per
+ * window; everything is enqueued on `stream` and the call does not wait.
+ * *n_records (may be NULL) receives the number of records written.
+ * Errors: RDX_EINVAL (n_windows < 0, every <= 0, ring_slots <= 0, null
+ * ring), RDX_EHIP. */
+rdx_status rdx_step_recorded(rdx_sim* sim, int64_t n_windows, int64_t every, int64_t* ring,
+                             int64_t ring_slots, int64_t* n_records, void* stream);
+
 rdx_status rdx_get_tau(const rdx_sim* sim, double* tau);
 rdx_status rdx_get_sizes(const rdx_sim* sim, int32_t* n_tets, int32_t* n_species,
                          int32_t* n_reactions);
@@ -360,7 +373,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 203
+#define RDX_ABI_VERSION 204
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

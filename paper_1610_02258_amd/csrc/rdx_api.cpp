@@ -61,6 +61,8 @@ rdx_status check_sim(const rdx_sim* s) {
   return RDX_OK;
 }
 
+constexpr size_t kRecStage = sizeof(unsigned long long) * kMaxRegions * kMaxSpecies;
+
 rdx_status set_rates_of(Engine& eng, Run& r, const double* kcst, int64_t n, hipStream_t stream) {
   const int64_t want = (int64_t)r.host.n_regions * (int64_t)r.host.R;
   if (n != want)
@@ -76,8 +78,7 @@ rdx_status region_counts_of(Engine& eng, const Run& r, int64_t* out, bool device
   if (!out) return set_error(RDX_EINVAL, "null output");
   // one device buffer per handle, made at the first call: the partial sums,
   // then a staging copy of the result for host output
-  constexpr size_t kStage = sizeof(unsigned long long) * kMaxRegions * kMaxSpecies;
-  if (!*rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(rec), kRegionScratchBytes + kStage));
+  if (!*rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(rec), kRegionScratchBytes + kRecStage));
   unsigned long long* stage = *rec + kRegionScratchBytes / sizeof(unsigned long long);
   if (device) return eng.region_counts(&r, *rec, reinterpret_cast<unsigned long long*>(out), stream);
   const rdx_status q = eng.region_counts(&r, *rec, stage, stream);
@@ -229,6 +230,35 @@ rdx_status rdx_step(rdx_sim* s, int64_t n_windows, void* stream) {
   rdx_status st = Engine::plan_steps(&s->run, n_windows);
   if (st != RDX_OK) return st;
   return s->eng.sequence({&s->run}, reinterpret_cast<hipStream_t>(stream));
+}
+
+rdx_status rdx_step_recorded(rdx_sim* s, int64_t n_windows, int64_t every, int64_t* ring, int64_t ring_slots,
+                             int64_t* n_records, void* stream) {
+  clear_error();
+  if (check_sim(s) != RDX_OK) return RDX_EINVAL;
+  if (n_records) *n_records = 0;
+  if (n_windows < 0 || every <= 0 || ring_slots <= 0 || !ring)
+    return set_error(RDX_EINVAL, "n_windows >= 0, every > 0, ring_slots > 0 and a device ring are required");
+  (void)hipSetDevice(s->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n_windows == 0) return RDX_OK;
+  if (!s->rec) RDX_HIP(hipMalloc(reinterpret_cast<void**>(&s->rec), kRegionScratchBytes + kRecStage));
+  // one sequence of n_windows plain windows with the reductions launched
+  // between them (one table upload for the whole call)
+  Engine::RecordHook hook;
+  hook.run = &s->run;
+  hook.every = every;
+  hook.scratch = s->rec;
+  hook.ring = reinterpret_cast<unsigned long long*>(ring);
+  hook.slots = ring_slots;
+  rdx_status q = Engine::plan_steps(&s->run, n_windows);
+  if (q != RDX_OK) return q;
+  s->eng.set_record_hook(&hook);
+  q = s->eng.sequence({&s->run}, st);
+  const int64_t written = s->eng.records_written();
+  s->eng.set_record_hook(nullptr);
+  if (n_records) *n_records = written;
+  return q;
 }
 
 rdx_status rdx_sync(rdx_sim* s, void* stream) {

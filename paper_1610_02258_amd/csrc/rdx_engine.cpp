@@ -562,6 +562,18 @@ rdx_status Engine::launch_plain(const StepArgs& a0, int64_t K, hipStream_t strea
     }
     hipError_t e = launch_window(a, stream, marks);
     if (e != hipSuccess) return set_error(RDX_EHIP, std::string("window launch: ") + hipGetErrorString(e));
+    if (rec_on_ && (k + 1) % rec_.every == 0) {
+      // the counts after this window sit in buffer (window + k + 1) & 1 (the
+      // run's window index advances when the sequence ends); the next window
+      // clears that buffer only after this reduction in stream order
+      const Run* r = rec_.run;
+      const int64_t slot = (int64_t)r->host.n_regions * r->host.S;
+      unsigned long long* out = rec_.ring + (rec_.records % rec_.slots) * slot;
+      e = launch_region_counts(r->cnt[(r->window + k + 1) & 1], r->region, r->host.T, r->host.S,
+                               r->host.n_regions, rec_.scratch, out, stream);
+      if (e != hipSuccess) return set_error(RDX_EHIP, std::string("record launch: ") + hipGetErrorString(e));
+      rec_.records += 1;
+    }
   }
   if (K > 0) RDX_HIP(launch_advance_base(d_base_, (int32_t)K, stream));
   return RDX_OK;
@@ -673,6 +685,13 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   };
 
   int64_t done = 0;
+  if (rec_on_) {  // records between windows: plain launches at the current shape
+    grids_for(n_tiles, shape_.fast_grid_div, &a.detect_grid, &a.main_grid);
+    a.ev_group_max = shape_.event_group;
+    st = launch_plain(a, K, stream);
+    if (st != RDX_OK) return st;
+    done = K;
+  }
   while (tuning_ && !timing_ && done < K && cand_next_ < candidates_.size()) {
     const ExecShape c = candidates_[cand_next_];
     const int64_t n = std::min<int64_t>(K - done, std::max(8, 2 * c.graph_windows));

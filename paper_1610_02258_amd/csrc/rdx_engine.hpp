@@ -131,6 +131,22 @@ class Engine {
   // out [n_regions*S], enqueued on `stream`; scratch holds kRegionScratchBytes.
   rdx_status region_counts(const Run* r, unsigned long long* scratch, unsigned long long* out,
                            hipStream_t stream);
+  // Recording inside a sequence: while set, sequence() launches plain
+  // windows (no tuning, no graphs) and after every `every`-th window of
+  // `run` writes its per-region sums to ring slot (records mod slots).
+  struct RecordHook {
+    const Run* run = nullptr;
+    int64_t every = 0;
+    unsigned long long* scratch = nullptr;
+    unsigned long long* ring = nullptr;
+    int64_t slots = 0;
+    int64_t records = 0;  // written so far
+  };
+  void set_record_hook(const RecordHook* h) {
+    rec_on_ = h != nullptr;
+    if (h) rec_ = *h;
+  }
+  int64_t records_written() const { return rec_.records; }
 
   // Plans (Algorithm 1 schedule): windows up to t_end, at most max_windows
   // (< 0: no limit); or n full windows.
@@ -207,6 +223,8 @@ class Engine {
 
   // graphs by (windows, grids); captured on a private stream
   hipStream_t capture_stream_ = nullptr;
+  RecordHook rec_{};
+  bool rec_on_ = false;
   std::map<std::pair<int, long long>, hipGraphExec_t> graphs_;
 
   ExecShape shape_;

@@ -30,6 +30,7 @@ SIGNATURES = {
     "rdx_get_counts": ([_p, _p, C.c_int, _p], C.c_int),
     "rdx_set_rate_constants": ([_p, _p, C.c_int64, _p], C.c_int),
     "rdx_region_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_step_recorded": ([_p, C.c_int64, C.c_int64, _p, C.c_int64, C.POINTER(C.c_int64), _p], C.c_int),
     "rdx_batch_set_rate_constants": ([_p, C.c_int32, _p, C.c_int64, _p], C.c_int),
     "rdx_batch_region_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
     "rdx_run": ([_p, C.c_double, _p], C.c_int),
@@ -290,6 +291,20 @@ class Sim:
         c = np.zeros((self.n_regions, self.S), np.int64)
         _check(lib().rdx_region_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_region_counts")
         return c
+
+    def step_recorded(self, n_windows: int, every: int, ring, stream=None) -> int:
+        """n_windows windows, recording per-region sums after every `every`
+        of them into the CUDA int64 ring [slots, n_regions, S] (slot j mod
+        slots); returns the number of records.  Does not wait."""
+        if not _is_torch_cuda(ring):
+            raise TypeError("the recording ring must be a CUDA tensor")
+        if ring.dtype != __import__("torch").int64 or not ring.is_contiguous() or \
+                tuple(ring.shape[1:]) != (self.n_regions, self.S):
+            raise ValueError(f"the ring must be contiguous int64 [slots, {self.n_regions}, {self.S}]")
+        n = C.c_int64()
+        _check(lib().rdx_step_recorded(self._h, int(n_windows), int(every), ring.data_ptr(), int(ring.shape[0]),
+                                       C.byref(n), _stream_ptr(stream)), "rdx_step_recorded")
+        return n.value
 
     def run(self, t_end: float, stream=None):
         _check(lib().rdx_run(self._h, float(t_end), _stream_ptr(stream)), "rdx_run")

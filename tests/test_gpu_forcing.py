@@ -202,3 +202,45 @@ def test_region_counts_sizes_and_wide_sums(rdx, oracle_lib, dims, n_regions):
     sim.region_counts(out=dev)
     assert np.array_equal(dev.cpu().numpy(), want)
     sim.close()
+
+
+def test_step_recorded_ring_wraps(rdx, oracle_lib):
+    """rdx_step_recorded: 26 windows, a record every 3 into a 5-slot ring
+    (8 records, so slots 0-2 hold records 5-7 and slots 3-4 records 3-4; the
+    last 2 windows are not recorded), against the oracle; then every 1 window
+    across graph-sized groups."""
+    import torch
+    rng = np.random.default_rng(75)
+    S, R = 9, 11
+    mesh = I.box_mesh(7, 5, 4, 0.5e-6, jitter=0.1, seed=10)
+    mesh.region = rng.integers(0, 3, mesh.n_tets).astype(np.uint8)
+    md = random_model(rng, S, R, 3)
+    counts = random_counts(rng, S, mesh.n_tets, mean=4.0)
+    _say(f"case: step_recorded, T={mesh.n_tets} S={S} R={R} regions=3")
+    sim = rdx.Sim(mesh.as_dict(), md, 44)
+    ref = oracle_lib.Instance(mesh.as_dict(), md, 44)
+    sim.set_counts(counts)
+    ref.reset(counts)
+    ring = torch.full((5, 3, S), -1, dtype=torch.int64, device="cuda:0")
+    assert sim.step_recorded(26, 3, ring) == 8
+    recs = []
+    for j in range(8):
+        ref.step(3)
+        recs.append(ref.region_counts())
+    ref.step(2)
+    got = ring.cpu().numpy()
+    for slot, j in enumerate([5, 6, 7, 3, 4]):
+        assert np.array_equal(got[slot], recs[j]), f"slot {slot}"
+    assert np.array_equal(sim.get_counts(), ref.counts)
+    ring2 = torch.full((20, 3, S), -1, dtype=torch.int64, device="cuda:0")
+    assert sim.step_recorded(20, 1, ring2) == 20
+    want = []
+    for j in range(20):
+        ref.step(1)
+        want.append(ref.region_counts())
+    assert np.array_equal(ring2.cpu().numpy(), np.stack(want))
+    st = sim.stats()
+    assert (st.ssa_events, st.moves, st.window_index) == (ref.tallies.ssa_events, ref.tallies.moves, ref.window)
+    with pytest.raises(rdx.RdxError):
+        sim.step_recorded(4, 0, ring2)
+    sim.close()
