@@ -141,7 +141,8 @@ rdx_status rdx_get_stats(rdx_sim* sim, rdx_stats* stats, void* stream);
  * this call; windows enqueued before it keep the old constants.  To switch
  * at a time t_s, run to t_s first (the window that crosses t_s is cut there,
  * as at any t_end).  Synchronises `stream` before it returns, so kcst may be
- * freed at once.  tau does not change (it depends on diffusion only).  The
+ * freed at once; for the same reason it may not be called while `stream` is
+ * being captured into a graph.  tau does not change (it depends on diffusion only).  The
  * table is not part of a checkpoint (rdx_save): set it again after rdx_load.
  * Errors: RDX_EINVAL (null handle, null kcst with n > 0, wrong n, a negative
  * or non-finite constant; the old table stays), RDX_EHIP. */
