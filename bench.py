@@ -15,10 +15,10 @@ launch time from HIP events on the launch stream, taken over a second pass of
 the same steps with per-kernel events), and the oracle timed on host cores on
 a bounded sample of the same workload.
 
-Two other modes print their own line instead: ``--sweep`` (the density and
-refinement series of the same box) and ``--forcing`` (time-varying influx and
-per-region recording on the dendrite workload, and the recording kernel's
-bandwidth).
+The line also carries, measured after the headline figures, the density and
+refinement series of the same box (``sweep``) and time-varying influx with
+per-region recording on the dendrite workload (``forcing``); ``--no-extra``
+leaves them out.  ``--sweep`` and ``--forcing`` print only that leg.
 """
 from __future__ import annotations
 
@@ -422,6 +422,8 @@ def main() -> int:
                     help="instead of the headline line, print the density and refinement series")
     ap.add_argument("--forcing", action="store_true",
                     help="instead of the headline line, print the forcing and recording measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="leave the density/refinement series and the forcing leg out of the headline line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload is a single simulation on one "
@@ -534,6 +536,15 @@ def main() -> int:
     if not args.no_serve:
         print("bench: serving leg", file=sys.stderr, flush=True)
         out["served"] = serve_leg(args.serve_requests)
+    if not args.no_extra:
+        # secondary measurements, outside the timed region; an exception here
+        # is reported in the line rather than losing the headline figures
+        for key, fn in (("sweep", lambda: sweep_leg(2)), ("forcing", forcing_leg)):
+            print(f"bench: {key} leg", file=sys.stderr, flush=True)
+            try:
+                out[key] = fn()
+            except Exception as e:  # noqa: BLE001
+                out[key] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
