@@ -264,3 +264,26 @@ def test_ten_times_density_full_size_prefix(rdx, oracle_lib):
         sim.step(1)
         ref.step(1)
         _assert_same(sim, ref, f"window {k}")
+
+
+def test_simple_model_whole_benchmarked_run(rdx, oracle_lib):
+    """The benchmarked step itself at full size: 480,000 tets, 10 species,
+    1e6 molecules, 100 ms = 220 windows, reset from device counts and run to
+    t_end on the graph path once the launch shape is tuned (as the timed
+    steps do), against the oracle's whole run: every count and tally."""
+    import torch
+    w = I.config_simple()
+    _say(f"case: whole benchmarked run, T={w.mesh.n_tets}, t_end={w.t_end}")
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):  # the first run also tunes the launch shape
+        sim.set_counts(c0, stream=stream)
+        sim.run(w.t_end, stream=stream)
+    assert sim.exec_options()["autotune"] == 0
+    ref = oracle_lib.Instance(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    ref.reset(w.counts)
+    ref.run(w.t_end)
+    _assert_same(sim, ref, "whole run")
+    assert ref.window == 220
+    sim.close()
