@@ -253,3 +253,38 @@ def test_batch_random_models_with_regions(rdx, oracle_lib, S, R):
             r.step(1)
         for i, r in enumerate(refs):
             _assert_run(b, i, r, f"window {k}")
+
+
+def test_ensemble_as_benchmarked_sampled(rdx, oracle_lib):
+    """The batched leg at its benchmarked size: 1024 uneven runs (T ~ logU(1e3,
+    5e4), 1 s each), every run reset from device counts in one launch and run
+    to t_end on graphs once the launch shape is tuned; every 64th run plus the
+    smallest and the largest against the oracle run alone."""
+    import torch
+    runs = I.ensemble_runs()
+    T = np.array([w.mesh.n_tets for w in runs])
+    idx = sorted(set(list(range(0, len(runs), 64)) + [int(T.argmin()), int(T.argmax())]))
+    _say(f"case: ensemble of {len(runs)} runs, {int(T.sum())} tets, sampled runs {idx}")
+    b = rdx.Batch([(w.mesh.as_dict(), w.model.as_dict(), w.seed) for w in runs])
+    c0 = [torch.from_numpy(np.ascontiguousarray(w.counts)).to("cuda:0") for w in runs]
+    stream = torch.cuda.current_stream()
+    t_end = [w.t_end for w in runs]
+    for _ in range(6):  # as the benchmark's warm-up: until the tuner has settled
+        b.set_counts_all(c0, stream=stream)
+        b.run(t_end, stream=stream)
+        torch.cuda.synchronize()
+        if not b.exec_options()["autotune"]:
+            break
+    assert b.exec_options()["autotune"] == 0
+    b.set_counts_all(c0, stream=stream)
+    b.run(t_end, stream=stream)
+    for i in idx:
+        w = runs[i]
+        ref = oracle_lib.Instance(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+        ref.reset(w.counts)
+        ref.run(w.t_end)
+        assert np.array_equal(b.get_counts(i), ref.counts), f"run {i}"
+        st = b.stats(i)
+        assert (st.ssa_events, st.moves, st.window_index) == (ref.tallies.ssa_events, ref.tallies.moves,
+                                                              ref.window), f"run {i}"
+    b.close()
