@@ -161,3 +161,30 @@ def test_random_structure_requests_with_regions(rdx, oracle_lib):
         assert info["stats"].ssa_events == ref.tallies.ssa_events
         assert info["stats"].moves == ref.tallies.moves
     srv.close()
+
+
+def test_benchmarked_request_stream_sampled(rdx, oracle_lib):
+    """The head of the served leg's request stream (48 Poisson requests,
+    T ~ logU(1296, 2e5), 10-species model, 100 ms each) through a server set
+    up as the benchmark's (16 GiB budget, 8 windows per tick); 8 requests
+    spread over the size range against the oracle run alone."""
+    reqs = I.request_stream(n_requests=48)
+    T = np.array([w.mesh.n_tets for _, w in reqs])
+    idx = [int(i) for i in np.argsort(T, kind="stable")[::6]][:8]
+    _say(f"case: served stream of {len(reqs)} requests, {int(T.sum())} tets, sampled {idx}")
+    model = reqs[0][1].model.as_dict()
+    srv = rdx.Server(model, hbm_budget_bytes=16 << 30, tick_windows=8)
+    tickets = [srv.submit(w.mesh.as_dict(), model, w.seed, w.counts, w.t_end) for _, w in reqs]
+    results = [srv.wait(tk, timeout_s=120.0) for tk in tickets]
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    srv.close()
+    for i in idx:
+        w = reqs[i][1]
+        ref = oracle_lib.Instance(w.mesh.as_dict(), model, w.seed)
+        ref.reset(w.counts)
+        ref.run(w.t_end)
+        got, info = results[i]
+        assert info["state"] == "done"
+        np.testing.assert_array_equal(got, ref.counts, err_msg=f"request {i}")
+        assert (info["stats"].ssa_events, info["stats"].moves) == (ref.tallies.ssa_events, ref.tallies.moves)
