@@ -254,10 +254,12 @@ def test_density_and_refinement_series(rdx, oracle_lib, density, h, extent):
         _assert_same(sim, ref, f"window {k}")
 
 
-def test_ten_times_density_full_size_prefix(rdx, oracle_lib):
-    """480,000 tets with 1e7 molecules (10x the benchmarked density): the
-    first windows compared on every count."""
-    w = I.config_simple_variant(10.0, 0.5)
+@pytest.mark.parametrize("density,h", [(10.0, 0.5), (1.0, 0.25)])
+def test_series_full_size_prefix(rdx, oracle_lib, density, h):
+    """The series at full size: 480,000 tets with 1e7 molecules (10x the
+    benchmarked density) and the refined 3,840,000-tet box (0.25 um cubes):
+    the first windows compared on every count."""
+    w = I.config_simple_variant(density, h)
     _say(f"case: {w.name}, T={w.mesh.n_tets}")
     sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
     for k in range(2):
