@@ -400,13 +400,18 @@ rdx_status Engine::set_rates(Run* r, const double* kcst, hipStream_t stream) {
   for (size_t i = 0; i < n; ++i)
     if (!(kcst[i] >= 0.0) || !std::isfinite(kcst[i]))
       return set_error(RDX_EINVAL, "rate constants must be finite and >= 0");
-  r->host.kcst.assign(kcst, kcst + n);
+  std::vector<double> old(kcst, kcst + n);
+  r->host.kcst.swap(old);
   const std::vector<double> kc = rate_image(model_host_, r->host);
   // stream-ordered: windows already enqueued keep the old constants; the
   // captured window graphs read the table through its pointer and need no
   // re-capture
-  RDX_HIP(hipMemcpyAsync(r->kcst, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, stream));
-  RDX_HIP(hipStreamSynchronize(stream));
+  hipError_t e = hipMemcpyAsync(r->kcst, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    r->host.kcst.swap(old);  // the host copy keeps describing the device table
+    return set_error(RDX_EHIP, std::string("rate table upload: ") + hipGetErrorString(e));
+  }
   return RDX_OK;
 }
 
