@@ -123,7 +123,11 @@ hipError_t launch_region_counts(const int32_t* counts, const uint8_t* region, in
   // tets; S * nb * kRecMaxRegions slots <= kRecMaxBlocks * kRecMaxRegions
   const int64_t want = ((int64_t)T + kRecThreads * kRecUnroll - 1) / (kRecThreads * kRecUnroll);
   const int64_t cap = kRecMaxBlocks / S > 0 ? kRecMaxBlocks / S : 1;
-  const int nb = (int)(want < cap ? want : cap);
+  int nb = (int)(want < cap ? want : cap);
+  // workgroups go to the 8 XCDs round-robin by linear id (x + s nb): with nb
+  // a multiple of 8, block x sits on the same XCD for every species, so the
+  // region labels of its tets come from that XCD's L2 after the first species
+  if (nb >= 8) nb &= ~7;
   static_assert((size_t)kRecMaxBlocks * kRecMaxRegions * sizeof(unsigned long long) <= kRegionScratchBytes,
                 "region-sum scratch too small");
   const dim3 grid((unsigned)nb, (unsigned)S);
