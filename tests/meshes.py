@@ -28,3 +28,15 @@ def model(D, reactions, species, n_regions=1):
             rhs[r, idx[s]] += 1
         k[:, r] = kv
     return dict(D=np.asarray(D, float), lhs=lhs, rhs=rhs, kcst=k)
+
+
+def mirror_pairs(n, scale=1e-6):
+    """n disjoint copies of the mirror pair, spaced 3 scale apart along x:
+    tets 2j and 2j + 1 share one face, and no other face is shared, so each
+    pair is an independent sample of the same two-tet system."""
+    one = mirror_pair(scale)
+    off = np.zeros((n, 1, 3))
+    off[:, 0, 0] = 3.0 * scale * np.arange(n)
+    verts = (one["verts"][None, :, :] + off).reshape(-1, 3)
+    tets = (one["tets"][None, :, :] + 5 * np.arange(n, dtype=np.int32)[:, None, None]).reshape(-1, 4)
+    return dict(verts=verts, tets=tets.astype(np.int32), region=None)
