@@ -434,15 +434,26 @@ rdx_status Engine::plan_until(Run* r, double t_end, int64_t max_windows) {
   if (!std::isfinite(t_end)) return set_error(RDX_EINVAL, "t_end must be finite");
   const double tau = r->host.tau;
   double t = r->t;
+  // the window index is a 32-bit field of the RNG counter: reject a horizon
+  // that needs more windows than are left before counting them one by one
+  const int64_t left = (int64_t)0xffffffffLL - r->window;
+  const int64_t cap = max_windows < 0 ? left : std::min(max_windows, left + 1);
+  if (t < t_end && (max_windows < 0 || max_windows > left)) {
+    const double est = (t_end - t) / tau;  // windows to t_end, to within roundings
+    if (!(est <= (double)left * (1.0 + 1e-9) + 2.0))
+      return set_error(RDX_EINVAL, "window index exceeds the 32-bit RNG counter field");
+  }
   int64_t steps = 0, full = 0;
   double tau_last = tau;
-  while (t < t_end && (max_windows < 0 || steps < max_windows)) {
+  while (t < t_end && steps <= cap && (max_windows < 0 || steps < max_windows)) {
     if (t + tau > t_end) {  // the last window is cut at t_end
       tau_last = t_end - t;
       t = t_end;
       steps += 1;
       break;
     }
+    if (!(t + tau > t))  // tau below the resolution of t: the loop would not advance
+      return set_error(RDX_EINVAL, "tau is below the floating-point resolution of t");
     t = t + tau;
     steps += 1;
     full += 1;
@@ -483,7 +494,21 @@ int rounds_grid(int64_t n_tiles, int resident) {
 }
 }  // namespace
 
-void Engine::grids_for(int64_t n_tiles, int div, int* detect, int* main) const {
+// Tile count rounded up to a coarse bucket (at most 1/8 above it): grids of
+// engines whose set of runs changes between sequences (servers, batches
+// whose runs finish at different times) then repeat, and so do the captured
+// graphs keyed by them.  The kernels read the exact count from the device
+// and leave surplus blocks idle.
+static int64_t bucket_tiles(int64_t n) {
+  if (n <= 64) return n;
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= n) ++lg;
+  const int64_t g = int64_t(1) << (lg - 3);
+  return (n + g - 1) / g * g;
+}
+
+void Engine::grids_for(int64_t n_tiles_exact, int div, int* detect, int* main) const {
+  const int64_t n_tiles = max_runs_ > 1 ? bucket_tiles(n_tiles_exact) : n_tiles_exact;
   int rd = 0, rm = 0;
   grid_resident(S_, R_, &rd, &rm);
   // detect kernel: one block per tile (light blocks, many resident per SIMD,

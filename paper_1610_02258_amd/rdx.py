@@ -187,6 +187,32 @@ def _is_torch_cuda(x) -> bool:
     return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
 
 
+def _current_device():
+    """The HIP device current in torch (the one a new handle binds to), or
+    None without a usable torch."""
+    try:
+        import torch
+        return torch.cuda.current_device() if torch.cuda.is_available() else None
+    except Exception:  # noqa: BLE001
+        return None
+
+
+def _check_device_tensor(t, dtype: str, numel: int, what: str, device=None):
+    """Raises unless t is a contiguous CUDA tensor of `dtype` with `numel`
+    elements on `device` (the library writes or reads exactly that many
+    through its device pointer)."""
+    if not _is_torch_cuda(t):
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what} is on cuda:{t.device.index}, the handle on cuda:{device}")
+    if str(t.dtype) != f"torch.{dtype}":
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+
+
 def _marshal(mesh: dict, model: dict):
     verts = np.ascontiguousarray(mesh["verts"], np.float64)
     tets = np.ascontiguousarray(mesh["tets"], np.int32)
@@ -237,6 +263,7 @@ class Sim:
         _check(L.rdx_create(C.byref(m), C.byref(md), int(seed) & (2**64 - 1), float(tau_override),
                             C.byref(h)), "rdx_create")
         self._h = h
+        self.device = _current_device()
         self.T, self.S, self.R = T, S, R
         self.n_regions = int(md.n_regions)
         tau = C.c_double()
@@ -259,7 +286,7 @@ class Sim:
     # -- state ---------------------------------------------------------------
     def set_counts(self, counts, stream=None):
         if _is_torch_cuda(counts):
-            assert counts.dtype.itemsize == 4 and counts.is_contiguous() and counts.numel() == self.S * self.T
+            _check_device_tensor(counts, "int32", self.S * self.T, "counts", self.device)
             _check(lib().rdx_set_counts(self._h, counts.data_ptr(), 1, _stream_ptr(stream)),
                    "rdx_set_counts")
         else:
@@ -268,6 +295,7 @@ class Sim:
 
     def get_counts(self, out=None, stream=None):
         if out is not None and _is_torch_cuda(out):
+            _check_device_tensor(out, "int32", self.S * self.T, "out", self.device)
             _check(lib().rdx_get_counts(self._h, out.data_ptr(), 1, _stream_ptr(stream)), "rdx_get_counts")
             return out
         c = np.zeros((self.S, self.T), np.int32)
@@ -286,6 +314,7 @@ class Sim:
         int64 tensor (e.g. one slot of a recording ring) the sums are written
         on `stream` without waiting."""
         if out is not None and _is_torch_cuda(out):
+            _check_device_tensor(out, "int64", self.n_regions * self.S, "out", self.device)
             _check(lib().rdx_region_counts(self._h, out.data_ptr(), 1, _stream_ptr(stream)), "rdx_region_counts")
             return out
         c = np.zeros((self.n_regions, self.S), np.int64)
@@ -301,6 +330,8 @@ class Sim:
         if ring.dtype != __import__("torch").int64 or not ring.is_contiguous() or \
                 tuple(ring.shape[1:]) != (self.n_regions, self.S):
             raise ValueError(f"the ring must be contiguous int64 [slots, {self.n_regions}, {self.S}]")
+        if self.device is not None and ring.device.index != self.device:
+            raise ValueError(f"the ring is on cuda:{ring.device.index}, the handle on cuda:{self.device}")
         n = C.c_int64()
         _check(lib().rdx_step_recorded(self._h, int(n_windows), int(every), ring.data_ptr(), int(ring.shape[0]),
                                        C.byref(n), _stream_ptr(stream)), "rdx_step_recorded")
@@ -390,6 +421,7 @@ class Batch:
         h = C.c_void_p()
         _check(L.rdx_batch_create(n, meshes, models, seeds, taus, C.byref(h)), "rdx_batch_create")
         self._h = h
+        self.device = _current_device()
         self._keep = None  # the library copied the inputs
         self.n = n
         self.tau = []
@@ -412,7 +444,7 @@ class Batch:
 
     def set_counts(self, i: int, counts, stream=None):
         if _is_torch_cuda(counts):
-            assert counts.dtype.itemsize == 4 and counts.is_contiguous() and counts.numel() == self.S * self.T[i]
+            _check_device_tensor(counts, "int32", self.S * self.T[i], "counts", self.device)
             _check(lib().rdx_batch_set_counts(self._h, i, counts.data_ptr(), 1, _stream_ptr(stream)),
                    "rdx_batch_set_counts")
         else:
@@ -422,14 +454,16 @@ class Batch:
 
     def set_counts_all(self, counts, stream=None):
         """Every run's counts from device tensors (one per run), in one launch."""
-        assert len(counts) == len(self.T)
-        for c, T in zip(counts, self.T):
-            assert _is_torch_cuda(c) and c.dtype.itemsize == 4 and c.is_contiguous() and c.numel() == self.S * T
+        if len(counts) != len(self.T):
+            raise ValueError(f"one counts tensor per run: {len(self.T)} expected, got {len(counts)}")
+        for j, (c, T) in enumerate(zip(counts, self.T)):
+            _check_device_tensor(c, "int32", self.S * T, f"counts[{j}]", self.device)
         ptrs = (C.c_void_p * len(counts))(*[c.data_ptr() for c in counts])
         _check(lib().rdx_batch_set_counts_all(self._h, ptrs, _stream_ptr(stream)), "rdx_batch_set_counts_all")
 
     def get_counts(self, i: int, out=None, stream=None):
         if out is not None and _is_torch_cuda(out):
+            _check_device_tensor(out, "int32", self.S * self.T[i], "out", self.device)
             _check(lib().rdx_batch_get_counts(self._h, i, out.data_ptr(), 1, _stream_ptr(stream)),
                    "rdx_batch_get_counts")
             return out
@@ -444,6 +478,7 @@ class Batch:
 
     def region_counts(self, i: int, out=None, stream=None):
         if out is not None and _is_torch_cuda(out):
+            _check_device_tensor(out, "int64", self.n_regions[i] * self.S, "out", self.device)
             _check(lib().rdx_batch_region_counts(self._h, i, out.data_ptr(), 1, _stream_ptr(stream)),
                    "rdx_batch_region_counts")
             return out
