@@ -162,6 +162,21 @@ rdx_status rdx_set_rate_constants(rdx_sim* sim, const double* kcst, int64_t n, v
  * Errors: RDX_EINVAL (null), RDX_EHIP. */
 rdx_status rdx_region_counts(rdx_sim* sim, int64_t* out, int is_device_ptr, void* stream);
 
+/* rdx_region_counts for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same sums into the device pointer out
+ * [n_regions*n_species] int64, enqueued on `stream` without waiting, with
+ * no hipMalloc, hipFree or other allocation.  The partial sums live in one
+ * static device array of 256 KiB per GPU, held until the process ends; its address is looked up at the first call on a device.
+ * Every call on one GPU shares that array and fully rewrites the part it
+ * reads, so nothing needs clearing, but calls that overlap in time on one
+ * GPU (different streams, or different host threads without ordering) race
+ * on it: order them on one stream.  Sizes: any n_tets; the slots needed for
+ * (n_tets, n_species) are checked against the array.
+ * Errors: RDX_EINVAL (null handle or out, or more scratch than the array
+ * holds), RDX_EHIP. */
+rdx_status rdx_region_counts_static(rdx_sim* sim, int64_t* out, void* stream);
+
 /* Recording at a fixed window interval (section 3.2 records every 0.02 ms):
  * n_windows full windows of tau, and after each `every` of them the
  * per-region sums (as rdx_region_counts) into slot j mod ring_slots of the
@@ -374,7 +389,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 204
+#define RDX_ABI_VERSION 205
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -197,6 +197,22 @@ rdx_status rdx_region_counts(rdx_sim* s, int64_t* out, int is_device_ptr, void* 
   return region_counts_of(s->eng, s->run, out, is_device_ptr != 0, &s->rec, reinterpret_cast<hipStream_t>(stream));
 }
 
+rdx_status rdx_region_counts_static(rdx_sim* s, int64_t* out, void* stream) {
+  clear_error();
+  if (check_sim(s) != RDX_OK) return RDX_EINVAL;
+  if (!out) return set_error(RDX_EINVAL, "null output");
+  (void)hipSetDevice(s->device);
+  unsigned long long* scratch = nullptr;
+  size_t cap = 0;
+  RDX_HIP(static_region_scratch(&scratch, &cap));
+  const size_t need = region_scratch_bytes(s->run.host.T, s->run.host.S);
+  if (need > cap)
+    return set_error(RDX_EINVAL, "the region sums need " + std::to_string(need) + " bytes of scratch, more than the " +
+                                     std::to_string(cap) + "-byte static array");
+  return s->eng.region_counts(&s->run, scratch, reinterpret_cast<unsigned long long*>(out),
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
 rdx_status rdx_set_counts(rdx_sim* s, const int32_t* counts, int is_device_ptr, void* stream) {
   clear_error();
   if (check_sim(s) != RDX_OK) return RDX_EINVAL;

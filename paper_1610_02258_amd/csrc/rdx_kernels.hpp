@@ -131,6 +131,13 @@ constexpr size_t kRegionScratchBytes = 4096 * 8 * 8;
 hipError_t launch_region_counts(const int32_t* counts, const uint8_t* region, int32_t T, int32_t S,
                                 int32_t n_regions, unsigned long long* scratch, unsigned long long* out,
                                 hipStream_t stream);
+// Scratch bytes launch_region_counts writes for T tets and S species (at most
+// kRegionScratchBytes).
+size_t region_scratch_bytes(int32_t T, int32_t S);
+// Device address and size of the static partial-sum array on the current
+// device, looked up once per device (hipGetSymbolAddress) and kept; no
+// allocation.
+hipError_t static_region_scratch(unsigned long long** ptr, size_t* bytes);
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_selftest_ln(const double* x, double* y, int64_t n, hipStream_t s);

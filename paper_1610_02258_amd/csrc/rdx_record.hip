@@ -18,6 +18,8 @@
 // exact, so the order of the additions does not change the result.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "rdx_kernels.hpp"
 
 namespace rdx {
@@ -111,7 +113,53 @@ __global__ __launch_bounds__(kRecThreads) void region_sums_finish_kernel(
   }
 }
 
+// Partial sums of the allocation-free recording entry point: a file-scope
+// device array, one copy on every device the library runs on, kept until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name stands for a host-side shadow, not a device address); it
+// passes the device address that hipGetSymbolAddress returns for the current
+// device.
+static __device__ __align__(256) unsigned long long scratch[kRegionScratchBytes / sizeof(unsigned long long)];
+
+// Slots the region-sum kernels write for (T, S): nb blocks per species, one
+// slot of kRecMaxRegions sums per block.
+int region_blocks(int32_t T, int32_t S) {
+  const int64_t want = ((int64_t)T + kRecThreads * kRecUnroll - 1) / (kRecThreads * kRecUnroll);
+  const int64_t cap = kRecMaxBlocks / S > 0 ? kRecMaxBlocks / S : 1;
+  int nb = (int)(want < cap ? want : cap);
+  // workgroups go to the 8 XCDs round-robin by linear id (x + s nb): with nb
+  // a multiple of 8, block x sits on the same XCD for every species, so the
+  // region labels of its tets come from that XCD's L2 after the first species
+  if (nb >= 8) nb &= ~7;
+  return nb;
+}
+
 }  // namespace
+
+size_t region_scratch_bytes(int32_t T, int32_t S) {
+  if (T <= 0 || S <= 0) return 0;
+  return (size_t)S * (size_t)region_blocks(T, S) * kRecMaxRegions * sizeof(unsigned long long);
+}
+
+hipError_t static_region_scratch(unsigned long long** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static unsigned long long* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {  // first call on this device (it is the current one)
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<unsigned long long*>(p);
+  }
+  *ptr = addr[dev];
+  *bytes = sizeof(scratch);
+  return hipSuccess;
+}
 
 hipError_t launch_region_counts(const int32_t* counts, const uint8_t* region, int32_t T, int32_t S,
                                 int32_t n_regions, unsigned long long* scratch, unsigned long long* out,
@@ -121,13 +169,7 @@ hipError_t launch_region_counts(const int32_t* counts, const uint8_t* region, in
     return hipErrorInvalidValue;
   // enough blocks to fill the chip, few enough that each thread sums several
   // tets; S * nb * kRecMaxRegions slots <= kRecMaxBlocks * kRecMaxRegions
-  const int64_t want = ((int64_t)T + kRecThreads * kRecUnroll - 1) / (kRecThreads * kRecUnroll);
-  const int64_t cap = kRecMaxBlocks / S > 0 ? kRecMaxBlocks / S : 1;
-  int nb = (int)(want < cap ? want : cap);
-  // workgroups go to the 8 XCDs round-robin by linear id (x + s nb): with nb
-  // a multiple of 8, block x sits on the same XCD for every species, so the
-  // region labels of its tets come from that XCD's L2 after the first species
-  if (nb >= 8) nb &= ~7;
+  const int nb = region_blocks(T, S);
   static_assert((size_t)kRecMaxBlocks * kRecMaxRegions * sizeof(unsigned long long) <= kRegionScratchBytes,
                 "region-sum scratch too small");
   const dim3 grid((unsigned)nb, (unsigned)S);

@@ -30,6 +30,7 @@ SIGNATURES = {
     "rdx_get_counts": ([_p, _p, C.c_int, _p], C.c_int),
     "rdx_set_rate_constants": ([_p, _p, C.c_int64, _p], C.c_int),
     "rdx_region_counts": ([_p, _p, C.c_int, _p], C.c_int),
+    "rdx_region_counts_static": ([_p, _p, _p], C.c_int),
     "rdx_step_recorded": ([_p, C.c_int64, C.c_int64, _p, C.c_int64, C.POINTER(C.c_int64), _p], C.c_int),
     "rdx_batch_set_rate_constants": ([_p, C.c_int32, _p, C.c_int64, _p], C.c_int),
     "rdx_batch_region_counts": ([_p, C.c_int32, _p, C.c_int, _p], C.c_int),
@@ -320,6 +321,15 @@ class Sim:
         c = np.zeros((self.n_regions, self.S), np.int64)
         _check(lib().rdx_region_counts(self._h, _np_ptr(c), 0, _stream_ptr(stream)), "rdx_region_counts")
         return c
+
+    def region_counts_static(self, out, stream=None):
+        """As region_counts into the CUDA int64 tensor `out` [n_regions, S],
+        through the entry point that allocates nothing (a static device
+        array holds the partial sums; calls on one GPU must not overlap)."""
+        _check_device_tensor(out, "int64", self.n_regions * self.S, "out", self.device)
+        _check(lib().rdx_region_counts_static(self._h, out.data_ptr(), _stream_ptr(stream)),
+               "rdx_region_counts_static")
+        return out
 
     def step_recorded(self, n_windows: int, every: int, ring, stream=None) -> int:
         """n_windows windows, recording per-region sums after every `every`
