@@ -85,7 +85,9 @@ typedef struct rdx_model {
 } rdx_model;
 
 /* Cumulative tallies since the last rdx_set_counts: windows run, voxel-steps
- * (tets x windows), applied SSA events, molecules moved between tets. */
+ * (tets x windows), applied SSA events, molecules moved between tets, and
+ * the nonzero (tet, species, face) moves -- each one an update of a
+ * neighbour's count, the term that prices the diffusion update's writes. */
 typedef struct rdx_stats {
   int64_t windows;
   int64_t voxel_steps;
@@ -93,6 +95,7 @@ typedef struct rdx_stats {
   int64_t moves;
   double t;
   int64_t window_index;
+  int64_t face_moves;
 } rdx_stats;
 
 typedef struct rdx_sim rdx_sim;
@@ -242,8 +245,12 @@ rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
  *   fast_grid_div  main kernel grid = resident grid / this (1, 2 or 4)
  *   graph_windows  windows per captured HIP graph, replayed as one launch;
  *                  1 = plain launches (1..256)
- *   event_group    most queued tiles whose listed tets one event block packs
- *                  into one 64-lane chunk (1..8; 0 = the default, 4) */
+ *   event_group    most queued tiles (tiles with a tet whose first SSA event
+ *                  falls in the window) one event block takes as a group,
+ *                  their listed tets packed into chunks of up to 64 lanes
+ *                  (1..64; 0 = the default, 4).  Where listed tets are sparse
+ *                  (one per tile), larger groups leave fewer, fuller event
+ *                  blocks and more blocks for the diffusion of every tet. */
 typedef struct rdx_exec_options {
   int32_t autotune;
   int32_t fast_grid_div;
@@ -389,7 +396,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 205
+#define RDX_ABI_VERSION 206
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -87,7 +87,7 @@ def _ptr(a: np.ndarray | None):
 
 class _Tallies(C.Structure):
     _fields_ = [("windows", C.c_int64), ("voxel_steps", C.c_int64),
-                ("ssa_events", C.c_int64), ("moves", C.c_int64)]
+                ("ssa_events", C.c_int64), ("moves", C.c_int64), ("face_moves", C.c_int64)]
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:
@@ -122,6 +122,7 @@ class Tallies:
     voxel_steps: int = 0
     ssa_events: int = 0
     moves: int = 0
+    face_moves: int = 0   # nonzero (tet, species, face) moves
 
 
 class OracleError(RuntimeError):
@@ -223,6 +224,7 @@ class Instance:
         self.tallies.voxel_steps += tal.voxel_steps
         self.tallies.ssa_events += tal.ssa_events
         self.tallies.moves += tal.moves
+        self.tallies.face_moves += tal.face_moves
 
     def run(self, t_end: float):
         t = C.c_double(self.t)

@@ -255,8 +255,11 @@ typedef struct {
   double tau;
 } os_instance;
 
+/* Tallies: windows, tets x windows, applied SSA events, molecules moved, and
+ * the nonzero (tet, species, face) moves -- the count M that prices the
+ * diffusion update's writes to neighbour counts. */
 typedef struct {
-  int64_t windows, voxel_steps, ssa_events, moves;
+  int64_t windows, voxel_steps, ssa_events, moves, face_moves;
 } os_tallies;
 
 static void os_free_instance(os_instance* I)
@@ -729,6 +732,7 @@ static int os_window(const os_instance* I, uint64_t seed, double tau_k, uint32_t
         if (out[k] > 0) {
           next[(size_t)s * T + I->nbr[4 * (size_t)i + k]] += (int32_t)out[k];
           tal->moves += out[k];
+          tal->face_moves += 1;
         }
     }
   }

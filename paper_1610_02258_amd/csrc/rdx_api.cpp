@@ -111,13 +111,14 @@ rdx_status start_run(Engine& eng, Run& r, const int32_t* counts, bool device, hi
 }
 
 rdx_status fill_stats(Engine& eng, const Run& r, rdx_stats* out) {
-  unsigned long long tal[2] = {0, 0};
+  unsigned long long tal[3] = {0, 0, 0};
   rdx_status st = eng.run_tally(&r, tal);
   if (st != RDX_OK) return st;
   out->windows = r.windows_run;
   out->voxel_steps = r.voxel_steps;
   out->ssa_events = (int64_t)tal[0];
   out->moves = (int64_t)tal[1];
+  out->face_moves = (int64_t)tal[2];
   out->t = r.t;
   out->window_index = r.window;
   return RDX_OK;
@@ -126,9 +127,9 @@ rdx_status fill_stats(Engine& eng, const Run& r, rdx_stats* out) {
 rdx_status apply_options(Engine& eng, const rdx_exec_options* o) {
   if (!o) return set_error(RDX_EINVAL, "null options");
   if (!(o->fast_grid_div == 1 || o->fast_grid_div == 2 || o->fast_grid_div == 4) || o->graph_windows < 1 ||
-      o->graph_windows > 256 || o->event_group < 0 || o->event_group > 8)
+      o->graph_windows > 256 || o->event_group < 0 || o->event_group > 64)
     return set_error(RDX_EINVAL,
-                     "fast_grid_div must be 1, 2 or 4, graph_windows in [1, 256], event_group in [0, 8]");
+                     "fast_grid_div must be 1, 2 or 4, graph_windows in [1, 256], event_group in [0, 64]");
   eng.set_shape(ExecShape{o->fast_grid_div, o->graph_windows, o->event_group ? o->event_group : 4});
   if (o->autotune) eng.set_autotune(true);
   return RDX_OK;
@@ -375,7 +376,7 @@ struct CheckpointHeader {
   int32_t version, T, S, pad;
   uint64_t seed;
   double t, tau;
-  int64_t window, windows_run, voxel_steps, events, moves;
+  int64_t window, windows_run, voxel_steps, events, moves, face_moves;
 };
 }  // namespace
 
@@ -395,7 +396,7 @@ rdx_status rdx_save(rdx_sim* s, void* buf, size_t* len, void* stream) {
   if (st != RDX_OK) return st;
   CheckpointHeader h;
   std::memset(&h, 0, sizeof h);
-  std::memcpy(h.magic, "RDXCKPT1", 8);
+  std::memcpy(h.magic, "RDXCKPT2", 8);
   h.version = rdx_version();
   h.T = r.host.T;
   h.S = r.host.S;
@@ -407,6 +408,7 @@ rdx_status rdx_save(rdx_sim* s, void* buf, size_t* len, void* stream) {
   h.voxel_steps = r.voxel_steps;
   h.events = stt.ssa_events;
   h.moves = stt.moves;
+  h.face_moves = stt.face_moves;
   std::memcpy(buf, &h, sizeof h);
   st = s->eng.download_counts(&r, reinterpret_cast<int32_t*>(static_cast<char*>(buf) + sizeof h), false,
                               reinterpret_cast<hipStream_t>(stream));
@@ -423,7 +425,7 @@ rdx_status rdx_load(rdx_sim* s, const void* buf, size_t len, void* stream) {
   std::memcpy(&h, buf, sizeof h);
   Run& r = s->run;
   const size_t n = (size_t)r.host.S * (size_t)r.host.T;
-  if (std::memcmp(h.magic, "RDXCKPT1", 8) != 0 || h.T != r.host.T || h.S != r.host.S || h.seed != r.seed ||
+  if (std::memcmp(h.magic, "RDXCKPT2", 8) != 0 || h.T != r.host.T || h.S != r.host.S || h.seed != r.seed ||
       h.tau != r.host.tau || h.window < 0 || h.window > (int64_t)0xffffffffLL || len < sizeof h + sizeof(int32_t) * n)
     return set_error(RDX_EINVAL, "checkpoint does not match this simulation");
   const int32_t* counts = reinterpret_cast<const int32_t*>(static_cast<const char*>(buf) + sizeof h);
@@ -436,7 +438,8 @@ rdx_status rdx_load(rdx_sim* s, const void* buf, size_t len, void* stream) {
   st = s->eng.reset_run(&r, strm);
   if (st == RDX_OK) st = s->eng.upload_counts(&r, counts, false, strm);
   if (st != RDX_OK) return st;
-  unsigned long long tal[2] = {(unsigned long long)h.events, (unsigned long long)h.moves};
+  unsigned long long tal[3] = {(unsigned long long)h.events, (unsigned long long)h.moves,
+                               (unsigned long long)h.face_moves};
   RDX_HIP(hipStreamSynchronize(strm));  // the tallies were cleared on this stream
   RDX_HIP(hipMemcpy(r.tally, tal, sizeof tal, hipMemcpyHostToDevice));  // into slot 0
   r.t = h.t;

@@ -175,7 +175,7 @@ size_t Engine::run_bytes(const HostInstance& I) {
   size_t b = 2 * align_up(4 * S * T) + align_up(16 * T) + align_up(32 * T) + align_up(8 * T);
   if (I.n_regions > 1) b += align_up(T);
   b += align_up(sizeof(double) * kMaxRegions * (32 + kLStride));  // rate constants, listing coefficients
-  b += align_up(sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t));  // tallies, error flag
+  b += align_up(sizeof(unsigned long long) * kTallyWords * kTallySlots + sizeof(int32_t));  // tallies, error flag
   return b;
 }
 
@@ -288,10 +288,10 @@ rdx_status Engine::add_run(Run* r, hipStream_t stream) {
   r->region = I.n_regions > 1 ? reinterpret_cast<uint8_t*>(carve(T)) : nullptr;
   r->kcst = reinterpret_cast<double*>(carve(sizeof(double) * kMaxRegions * (32 + kLStride)));
   r->lcoef = r->kcst + kMaxRegions * 32;
-  const size_t misc_bytes = sizeof(unsigned long long) * 2 * kTallySlots + sizeof(int32_t);
+  const size_t misc_bytes = sizeof(unsigned long long) * kTallyWords * kTallySlots + sizeof(int32_t);
   char* misc = carve(misc_bytes);
   r->tally = reinterpret_cast<unsigned long long*>(misc);
-  r->err = reinterpret_cast<int32_t*>(misc + sizeof(unsigned long long) * 2 * kTallySlots);
+  r->err = reinterpret_cast<int32_t*>(misc + sizeof(unsigned long long) * kTallyWords * kTallySlots);
 
   // host images of the interleaved couplings and the padded rate table; the
   // copies are synchronous so the images can go when this returns
@@ -338,7 +338,7 @@ void Engine::remove_run(Run* r, hipStream_t stream) {
 rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
   const size_t n = (size_t)r->host.S * (size_t)r->host.T;
   RDX_HIP(hipMemsetAsync(r->cnt[(r->window + 1) & 1], 0, sizeof(int32_t) * n, stream));
-  RDX_HIP(hipMemsetAsync(r->tally, 0, sizeof(unsigned long long) * 2 * kTallySlots, stream));
+  RDX_HIP(hipMemsetAsync(r->tally, 0, sizeof(unsigned long long) * kTallyWords * kTallySlots, stream));
   RDX_HIP(hipMemsetAsync(r->err, 0, sizeof(int32_t), stream));
   return RDX_OK;
 }
@@ -649,8 +649,9 @@ void Engine::set_autotune(bool on) {
   cand_next_ = 0;
   if (!on) return;
   // the first entry is a warm-up of the default shape and is not scored
-  candidates_ = {ExecShape{1, 1, 4}, ExecShape{1, 1, 4}, ExecShape{2, 1, 4}, ExecShape{1, 8, 4},
-                 ExecShape{2, 8, 4}, ExecShape{4, 8, 4}, ExecShape{1, 8, 8}};
+  candidates_ = {ExecShape{1, 1, 4},  ExecShape{1, 1, 4},  ExecShape{2, 1, 4}, ExecShape{1, 8, 4},
+                 ExecShape{2, 8, 4},  ExecShape{4, 8, 4},  ExecShape{1, 8, 8}, ExecShape{1, 8, 16},
+                 ExecShape{1, 8, 64}, ExecShape{1, 1, 64}};
 }
 
 rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
@@ -805,14 +806,12 @@ rdx_status Engine::run_error(const Run* r) const {
   return RDX_OK;
 }
 
-rdx_status Engine::run_tally(const Run* r, unsigned long long tal[2]) const {
-  unsigned long long slots[2 * kTallySlots];
+rdx_status Engine::run_tally(const Run* r, unsigned long long tal[3]) const {
+  unsigned long long slots[kTallyWords * kTallySlots];
   RDX_HIP(hipMemcpy(slots, r->tally, sizeof slots, hipMemcpyDeviceToHost));
-  tal[0] = tal[1] = 0;
-  for (int j = 0; j < kTallySlots; ++j) {
-    tal[0] += slots[2 * j];
-    tal[1] += slots[2 * j + 1];
-  }
+  tal[0] = tal[1] = tal[2] = 0;
+  for (int j = 0; j < kTallySlots; ++j)
+    for (int q = 0; q < 3; ++q) tal[q] += slots[kTallyWords * j + q];
   return RDX_OK;
 }
 

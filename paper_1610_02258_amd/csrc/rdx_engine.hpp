@@ -64,7 +64,7 @@ struct Run {
   uint8_t* region = nullptr;  // only with more than one region
   double* kcst = nullptr;     // [8][32], then the listing coefficients
   double* lcoef = nullptr;    // [8][kLStride]
-  unsigned long long* tally = nullptr;  // [kTallySlots][2]
+  unsigned long long* tally = nullptr;  // [kTallySlots][kTallyWords]
   int32_t* err = nullptr;
   double t = 0.0;
   int64_t window = 0;
@@ -168,7 +168,8 @@ class Engine {
   rdx_status kernel_times(rdx_kernel_times* out, bool reset);
 
   rdx_status run_error(const Run* r) const;  // device error flag of one run (synchronous)
-  rdx_status run_tally(const Run* r, unsigned long long tal[2]) const;
+  // SSA events, molecules moved, nonzero (tet, species, face) moves
+  rdx_status run_tally(const Run* r, unsigned long long tal[3]) const;
 
   int S() const { return S_; }
   int R() const { return R_; }

@@ -108,12 +108,14 @@ struct Draw32 {
     ++call;
     pos = 0;
   }
-  __device__ __forceinline__ double u() {
+  // The next 32-bit word of the stream, and the uniform w 2^-32 it stands for.
+  __device__ __forceinline__ uint32_t word() {
     if (pos == 4) refill();
     const uint32_t w = pos == 0 ? w0 : (pos == 1 ? w1 : (pos == 2 ? w2 : w3));
     ++pos;
-    return (double)w * 0x1p-32;
+    return w;
   }
+  __device__ __forceinline__ double u() { return (double)word() * 0x1p-32; }
 };
 
 // ------------------------------------------------------------------ ln ----
@@ -365,75 +367,241 @@ __device__ __forceinline__ int wave_scan_add(int v) {
   return v;
 }
 
-// Leavers of one item and their faces.  m = nbar stochastically rounded (a
-// draw only when nbar is fractional).  With m <= 16 every molecule draws one
-// 32-bit uniform u and leaves when u < p, to the first face k before the last
-// face present with u < p cum_k, else to the last face; once npost molecules
-// have left the rest stay.  With m > 16, n = min(Bin(m, p), npost) leavers
-// each draw one uniform for their face (same rule with p replaced by 1).
-// Both are exact samplers of binomial leavers split among the faces in
-// proportion to the face couplings.  ga = (G, cum0), gb = (cum1, cum2).
+// Diffusion items.  An item is one (tet, species) pair of a window: m trials
+// of leaving, m = nbar stochastically rounded (a draw only when nbar is
+// fractional).  With m <= 16 every molecule draws one 32-bit uniform u and
+// leaves when u < p, to the first face k before the last face present with
+// u < p cum_k, else to the last face; once npost molecules have left the
+// rest stay.  With m > 16, n = min(Bin(m, p), npost) leavers each draw one
+// uniform for their face (same rule with p replaced by 1).  Both are exact
+// samplers of binomial leavers split among the faces in proportion to the
+// face couplings.
+//
+// The face draws of an item are the words w0, w0 + 1, ... of its species
+// stream, w0 the words the rounding and the binomial used; word j is word
+// j mod 4 of Philox call j / 4.  So once w0 and the number of draws are
+// known, any lane can make any of them: a round of up to 64 items is set up
+// one item per lane, then the Philox calls of all its items are shared out
+// over the 64 lanes, each call's words tested against the item's integer
+// thresholds and the face counts summed per item in LDS.  A wave no longer
+// waits on its largest item, and the results are those of the item's own
+// sequential walk, bit for bit.  (With m <= 16 and m > npost the cap can
+// bind in the middle of the walk; such an item -- only a tet whose counts
+// changed in the window can have one -- is walked by its own lane.)
 constexpr int kSmallM = 16;
 
 struct ItemMoves {
   int n, o0, o1, o2, o3;
 };
 
-__device__ __forceinline__ ItemMoves sample_item(uint32_t key0, uint32_t key1, uint32_t window,
-                                                 int ti, int s, double nbar, int npost, int4 nb,
-                                                 double2 ga, double2 gb, double tauDs) {
-  const int last = nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
-  Draw32 sp(key0, key1, 1u + (uint32_t)s, (uint32_t)ti, window);
-  sp.prime();
-  const double fl = floor(nbar);
-  const double frac = nbar - fl;
-  long long m = (long long)fl;
-  if (frac > 0.0) {
-    if (sp.u() < frac) m += 1;
-  }
-  double p = tauDs * ga.x;
-  if (p > 1.0) p = 1.0;
-  long long trials;
-  double scale;
-  if (m <= kSmallM) {
-    trials = m;
-    scale = p;
-  } else {
-    long long nb_ = binom(m, p, sp);
-    trials = nb_ > npost ? (long long)npost : nb_;
-    scale = 1.0;
-  }
-  const double t0 = scale * ga.y, t1 = scale * gb.x, t2 = scale * gb.y;
-  int n = 0, o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-  // the draws in stream order, four words per Philox call: the words left in
-  // the current call, then whole calls; word q of a call is a register, so
-  // no draw needs a run-time select
-  long long j = 0;
-  int q0 = sp.pos;
-  while (j < trials) {
-    if (q0 == 4) {
-      sp.refill();
-      q0 = 0;
-    }
+// A draw w stands for the uniform w 2^-32, and w 2^-32 < t holds exactly
+// when w < ceil(t 2^32) (t 2^32 is exact in binary64).  For t in [0, 1] the
+// threshold is at most 2^32: returned as a 32-bit value, with `full` set when
+// it is 2^32 (every draw passes).
+__device__ __forceinline__ uint32_t draw_threshold(double t, bool& full) {
+  const double c = ceil(t * 0x1p32);
+  full = c >= 0x1p32;
+  return full ? 0xffffffffu : (uint32_t)c;
+}
+
+// One round's item records and per-item face sums.
+struct ItemLds {
+  uint32_t thr[4][kWave];         // thresholds of faces 0-2 and of leaving
+  uint32_t info[kWave];           // bit k: threshold k is 2^32 or more (every draw passes it)
+                                  // or face k is at or after the last face; bits 8-11 species
+  uint32_t tet[kWave];            // run-local tet (the stream's counter)
+  uint32_t w0[kWave];             // first face draw
+  uint32_t nw[kWave];             // face draws
+  unsigned long long off[kWave];  // first call of the item in the round's list of calls
+  uint32_t face[4][kWave];        // leavers by face
+  int slot[kWave];                // item whose calls start at each call of a batch
+};
+
+// What a lane brings to a round: its item, or valid == false.
+struct ItemIn {
+  bool valid;
+  int sp;          // species
+  uint32_t tet;    // run-local tet index
+  double nbar;     // mean occupancy (the count itself when nothing changed it)
+  int npost;       // count after the reactions
+  double p;        // min(1, tau_k D_s G)
+  int last;        // last face with a neighbour
+  double c0, c1, c2;  // cumulative split fractions
+};
+
+__device__ __forceinline__ unsigned long long wave_scan_add_u64(unsigned long long v) {
+  const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q >= q0 && j < trials) {
-        const uint32_t w = q == 0 ? sp.w0 : (q == 1 ? sp.w1 : (q == 2 ? sp.w2 : sp.w3));
-        const double u = (double)w * 0x1p-32;
-        if (u < scale && n < npost) {
-          const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
-          o0 += f == 0;
-          o1 += f == 1;
-          o2 += f == 2;
-          o3 += f == 3;
-          ++n;
-        }
-        ++j;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const unsigned long long u = __shfl_up(v, d, kWave);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int wave_scan_max(int v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int u = __shfl_up(v, d, kWave);
+    if (lane >= d && u > v) v = u;
+  }
+  return v;
+}
+
+// Face of a leaving draw w: the number of faces k < last whose threshold w
+// reaches (the thresholds rise with k; faces at or after `last` carry the
+// "never" bit), and whether w leaves at all.
+__device__ __forceinline__ int draw_face(uint32_t w, uint32_t t0, uint32_t t1, uint32_t t2, uint32_t full) {
+  return (int)(((full & 1u) == 0u && w >= t0)) + (int)(((full & 2u) == 0u && w >= t1)) +
+         (int)(((full & 4u) == 0u && w >= t2));
+}
+
+__device__ __forceinline__ bool draw_leaves(uint32_t w, uint32_t ts, uint32_t full) {
+  return (full & 8u) != 0u || w < ts;
+}
+
+// Leavers by face of the words [w0, w0 + nw) found in Philox call `call`
+// (words 4 call .. 4 call + 3), a byte per face.
+__device__ __forceinline__ uint32_t call_leavers(uint32_t key0, uint32_t key1, uint32_t stream, uint32_t tet,
+                                                 uint32_t window, uint32_t call, uint32_t w0, uint32_t nw,
+                                                 uint32_t t0, uint32_t t1, uint32_t t2, uint32_t ts,
+                                                 uint32_t full) {
+  uint32_t x0 = call, x1 = stream, x2 = tet, x3 = window;
+  philox4x32_10(x0, x1, x2, x3, key0, key1);
+  uint32_t packed = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+    const uint32_t idx = 4u * call + (uint32_t)q;
+    if (idx >= w0 && idx - w0 < nw && draw_leaves(w, ts, full)) packed += 1u << (8 * draw_face(w, t0, t1, t2, full));
+  }
+  return packed;
+}
+
+__device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, const ItemIn& it, ItemLds& X) {
+  const int lane = threadIdx.x;
+  uint32_t w0 = 0, nw = 0, calls = 0, full = 0;
+  uint32_t th[4] = {0u, 0u, 0u, 0u};
+  uint32_t own = 0;     // leavers by face drawn on this lane, a byte each
+  bool walked = false;  // this lane's face counts are in X.face
+  if (it.valid) {
+    Draw32 st(key0, key1, 1u + (uint32_t)it.sp, it.tet, window);
+    const double fl = floor(it.nbar);
+    const double frac = it.nbar - fl;
+    long long m = (long long)fl;
+    uint32_t used = 0;  // words taken before the face draws
+    if (frac > 0.0) {
+      if (st.u() < frac) m += 1;
+      used = 1;
+    }
+    const double p = it.p;
+    double scale = p;
+    long long trials = 0;
+    if (m > 0 && p > 0.0) {
+      if (m <= kSmallM) {
+        trials = m;
+        walked = m > (long long)it.npost;  // the cap may bind mid-walk
+      } else {
+        const long long n = binom(m, p, st);
+        if (p < 1.0) used += (uint32_t)((m + 999) / 1000);
+        trials = n > (long long)it.npost ? (long long)it.npost : n;
+        scale = 1.0;
       }
     }
-    q0 = 4;
+    bool f0, f1, f2, fs;
+    th[0] = draw_threshold(scale * it.c0, f0);
+    th[1] = draw_threshold(scale * it.c1, f1);
+    th[2] = draw_threshold(scale * it.c2, f2);
+    th[3] = draw_threshold(scale, fs);
+    full = (f0 || it.last <= 0 ? 1u : 0u) | (f1 || it.last <= 1 ? 2u : 0u) | (f2 || it.last <= 2 ? 4u : 0u) |
+           (fs ? 8u : 0u);
+    if (walked) {  // in stream order, after the rounding draw
+#pragma unroll
+      for (int k = 0; k < 4; ++k) X.face[k][lane] = 0u;
+      int n = 0;
+      for (long long j = 0; j < trials; ++j) {
+        const uint32_t w = st.word();
+        if (draw_leaves(w, th[3], full) && n < it.npost) {
+          X.face[draw_face(w, th[0], th[1], th[2], full)][lane] += 1u;
+          ++n;
+        }
+      }
+      trials = 0;
+    }
+    w0 = used;
+    nw = (uint32_t)trials;
+    if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
+    // an item whose draws lie in one Philox call draws it on its own lane
+    if (calls == 1u) {
+      own = call_leavers(key0, key1, 1u + (uint32_t)it.sp, it.tet, window, w0 >> 2, w0, nw, th[0], th[1], th[2],
+                         th[3], full);
+      calls = 0u;
+    }
   }
-  return ItemMoves{n, o0, o1, o2, o3};
+  // the calls of the other items are shared out over the wave
+  const bool shared = __ballot(calls > 0u) != 0ull;  // uniform
+  if (shared) {
+    const unsigned long long c64 = calls;
+    const unsigned long long incl = wave_scan_add_u64(c64);
+    const unsigned long long first = incl - c64;
+    const unsigned long long total = __shfl(incl, kWave - 1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      X.thr[k][lane] = th[k];
+      if (!walked) X.face[k][lane] = 0u;
+    }
+    X.info[lane] = full | ((uint32_t)(it.valid ? it.sp : 0) << 8);
+    X.tet[lane] = it.tet;
+    X.w0[lane] = w0;
+    X.nw[lane] = nw;
+    X.off[lane] = first;
+    wave_sync();
+    // batches of 64 calls: the item holding call b0 is the last lane with
+    // calls whose first call is at most b0; the items starting inside the
+    // batch mark their first call, and a running maximum over the lanes
+    // carries each mark to the calls after it
+    for (unsigned long long b0 = 0; b0 < total; b0 += kWave) {
+      const unsigned long long held = __ballot(calls > 0u && first <= b0);
+      const int i_lo = 63 - __builtin_clzll(held);
+      X.slot[lane] = -1;
+      wave_sync();
+      if (calls > 0u && first > b0 && first < b0 + kWave) X.slot[(int)(first - b0)] = lane;
+      wave_sync();
+      const int v = X.slot[lane];
+      const int item = wave_scan_max(v > i_lo ? v : i_lo);
+      const unsigned long long t = b0 + (unsigned long long)lane;
+      if (t < total) {
+        const uint32_t iw0 = X.w0[item], info = X.info[item];
+        const uint32_t call = (iw0 >> 2) + (uint32_t)(t - X.off[item]);
+        const uint32_t packed =
+            call_leavers(key0, key1, 1u + ((info >> 8) & 15u), X.tet[item], window, call, iw0, X.nw[item],
+                         X.thr[0][item], X.thr[1][item], X.thr[2][item], X.thr[3][item], info);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t c = (packed >> (8 * k)) & 0xffu;
+          if (c) atomicAdd(&X.face[k][item], c);
+        }
+      }
+      wave_sync();  // the slots are rebuilt for the next batch
+    }
+  }
+  ItemMoves r{0, 0, 0, 0, 0};
+  if (it.valid) {
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = ((own >> (8 * k)) & 0xffu) + (shared || walked ? X.face[k][lane] : 0u);
+    r.o0 = (int)o[0];
+    r.o1 = (int)o[1];
+    r.o2 = (int)o[2];
+    r.o3 = (int)o[3];
+    r.n = r.o0 + r.o1 + r.o2 + r.o3;
+  }
+  return r;
+}
+
+__device__ __forceinline__ int last_face(int4 nb) {
+  return nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
 }
 
 // Tile schedule of a persistent block: the blocks are dispatched round-robin
@@ -517,7 +685,7 @@ __device__ __forceinline__ void load_tet(const TileCtx& c, int S, int i, TetData
 }
 
 __device__ __forceinline__ unsigned long long* tally_slot(const StepArgs& A, int run) {
-  return as_const(A.runs)[run].tally + 2 * (blockIdx.x & (kTallySlots - 1));
+  return as_const(A.runs)[run].tally + kTallyWords * (blockIdx.x & (kTallySlots - 1));
 }
 
 __device__ __forceinline__ int step_index(const StepArgs& A) {
@@ -653,6 +821,7 @@ struct DiffusionLds {
   uint32_t item[SMAX * kWave];  // packed items: count << 10 | lane << 4 | species
   int4 nbr[kWave];
   double2 geo[2][kWave];        // (G, cum0), (cum1, cum2)
+  ItemLds x;                    // the current round of items
 };
 
 // Lanes of an event chunk: the propensity table takes RMAX doubles per lane,
@@ -670,7 +839,10 @@ struct EventLds {
   uint32_t delta_w[32 * 16 / 4];        // int8 [32][16]
   uint32_t deps_w[32 * 2];              // uint64 [32]: reactions whose propensity a reaction changes
   uint32_t kc_w[kMaxRegions * 32 * 2];  // double [8][32]
-  double a[RMAX][CW];                   // propensities of the chunk's tets, one column per lane
+  union {
+    double a[RMAX][CW];                 // propensities of the chunk's tets, one column per lane
+    ItemLds x;                          // then the rounds of their diffusion items
+  };
   double td[SMAX];                      // tau_k D_s of the tile's run
   double nbar[kWave];                   // mean occupancy of the round's items
   int npost[kWave];                     // post-reaction count of the round's items
@@ -695,7 +867,7 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(b, G, n_tiles);
   int cache_run = -1;
-  unsigned long long n_moved = 0;
+  unsigned long long n_moved = 0, n_faces = 0;
   uint32_t key0 = 0, key1 = 0, dmask = 0;  // per-run constants (uniform)
 
   TileCtx cc, nc;
@@ -717,9 +889,11 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
     const bool active = i < T;
     if (run_active && cc.run != cache_run) {
       if (cache_run >= 0) {  // tallies are kept per run
-        const unsigned long long mv = wave_sum(n_moved);
+        const unsigned long long mv = wave_sum(n_moved), fm = wave_sum(n_faces);
         if (lane == 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
+        if (lane == 0 && fm) atomicAdd(tally_slot(A, cache_run) + 2, fm);
         n_moved = 0;
+        n_faces = 0;
       }
       key0 = rd->key0;
       key1 = rd->key1;
@@ -759,51 +933,87 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
         for (int s = 0; s < SMAX; ++s)
           if (((dmask >> s) & 1u) && n_own[s] > 0) mask |= 1u << s;
       }
-      const int cnt = __popc(mask);
-      const int incl = wave_inclusive_scan(cnt);
-      const int total = __shfl(incl, kWave - 1);
-      int pos = incl - cnt;
-      int errbits = 0;
+      // items with more than 16 molecules (a binomial count each) first, so
+      // that few rounds wait on a binomial; then the rest; species-major
+      // within each class
+      int total = 0, errbits = 0;
+      const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+      for (int cls = 0; cls < 2; ++cls) {
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) {
+          const int n = n_own[s];
+          const bool has = ((mask >> s) & 1u) && ((n > kSmallM) == (cls == 0));
+          const unsigned long long bs = __ballot(has);
+          if (has)  // a count of 2^22 or more does not fit the packed field (0 marks it)
+            L.item[total + __popcll(bs & below)] =
+                ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
+          total += (int)__popcll(bs);
+        }
+      }
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) {
         const int n = n_own[s];
         if (n > kCountCap) errbits |= kErrOverflow;
-        if ((mask >> s) & 1u) {
-          // a count of 2^22 or more does not fit the packed field (0 marks it)
-          L.item[pos++] = ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
-        }
         // the accumulator starts with what cannot leave
         L.acc[s][lane] = ((mask >> s) & 1u) || event || !active ? 0 : n;
       }
       wave_sync();
 
       const int base = cc.base;
-      for (int j = lane; j < total; j += kWave) {
-        const uint32_t it = L.item[j];
-        const int Ln = (int)((it >> 4) & 63);
-        const int sp = (int)(it & 15);
-        int m = (int)(it >> 10);
-        if (m == 0) m = cc.cin[(size_t)sp * T + base + Ln];  // an unpacked large count
-        const int4 tnb = L.nbr[Ln];
-        const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
-        const double tds = L.tauD[sp];
-        const ItemMoves mv = sample_item(key0, key1, cc.window, base + Ln, sp, (double)m, m, tnb, ga, gb, tds);
-        // own remainder and moves to the tile's own tets go to LDS, the rest
-        // to the next count buffer
-        int32_t* __restrict__ out_s = cc.cout + (size_t)sp * T;
-        if (m != mv.n) atomicAdd(&L.acc[sp][Ln], m - mv.n);
-#define RDX_DEPOSIT(t, v)                                               \
-        if (v) {                                                        \
-          const unsigned off = (unsigned)((t) - base);                   \
-          if (off < (unsigned)kWave) atomicAdd(&L.acc[sp][off], (v));    \
-          else atomicAdd(out_s + (t), (v));                              \
+      for (int r0 = 0; r0 < total; r0 += kWave) {
+        ItemIn in;
+        in.valid = lane < total - r0;
+        int Ln = 0, sp = 0, m = 0;
+        int4 tnb = make_int4(-1, -1, -1, -1);
+        if (in.valid) {
+          const uint32_t itw = L.item[r0 + lane];
+          Ln = (int)((itw >> 4) & 63);
+          sp = (int)(itw & 15);
+          m = (int)(itw >> 10);
+          if (m == 0) m = cc.cin[(size_t)sp * T + base + Ln];  // an unpacked large count
+          tnb = L.nbr[Ln];
+          const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
+          double pr = L.tauD[sp] * ga.x;
+          if (pr > 1.0) pr = 1.0;
+          in.sp = sp;
+          in.tet = (uint32_t)(base + Ln);
+          in.nbar = (double)m;
+          in.npost = m;
+          in.p = pr;
+          in.last = last_face(tnb);
+          in.c0 = ga.y;
+          in.c1 = gb.x;
+          in.c2 = gb.y;
+        } else {
+          in.sp = 0;
+          in.tet = 0u;
+          in.nbar = 0.0;
+          in.npost = 0;
+          in.p = 0.0;
+          in.last = 0;
+          in.c0 = in.c1 = in.c2 = 0.0;
         }
-        RDX_DEPOSIT(tnb.x, mv.o0)
-        RDX_DEPOSIT(tnb.y, mv.o1)
-        RDX_DEPOSIT(tnb.z, mv.o2)
-        RDX_DEPOSIT(tnb.w, mv.o3)
+        const ItemMoves mv = item_round(key0, key1, cc.window, in, L.x);
+        if (in.valid) {
+          // own remainder and moves to the tile's own tets go to LDS, the
+          // rest to the next count buffer
+          int32_t* __restrict__ out_s = cc.cout + (size_t)sp * T;
+          if (m != mv.n) atomicAdd(&L.acc[sp][Ln], m - mv.n);
+#define RDX_DEPOSIT(t, v)                                               \
+          if (v) {                                                      \
+            const unsigned off = (unsigned)((t) - base);                 \
+            if (off < (unsigned)kWave) atomicAdd(&L.acc[sp][off], (v));  \
+            else atomicAdd(out_s + (t), (v));                            \
+            ++n_faces;                                                   \
+          }
+          RDX_DEPOSIT(tnb.x, mv.o0)
+          RDX_DEPOSIT(tnb.y, mv.o1)
+          RDX_DEPOSIT(tnb.z, mv.o2)
+          RDX_DEPOSIT(tnb.w, mv.o3)
 #undef RDX_DEPOSIT
-        n_moved += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+          n_moved += (unsigned long long)mv.n;
+        }
       }
       wave_sync();
       // coalesced flush of the tile's own tets (other tiles add into them too)
@@ -829,8 +1039,9 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
     cmask = nmask;
   }
 
-  const unsigned long long mv = wave_sum(n_moved);
+  const unsigned long long mv = wave_sum(n_moved), fm = wave_sum(n_faces);
   if (lane == 0 && cache_run >= 0 && mv) atomicAdd(tally_slot(A, cache_run) + 1, mv);
+  if (lane == 0 && cache_run >= 0 && fm) atomicAdd(tally_slot(A, cache_run) + 2, fm);
 }
 
 // One event chunk: up to CW listed tets of one run (worklist slot `slot` on
@@ -912,7 +1123,7 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
     L.geo[0][lane] = ga;
     L.geo[1][lane] = gb;
 
-    unsigned long long n_ev = 0, n_mv = 0;
+    unsigned long long n_ev = 0, n_mv = 0, n_fm = 0;
     int errbits = 0;
     uint32_t mask = 0;
     double nbv[SMAX];  // mean occupancies of the tet's items
@@ -1032,28 +1243,56 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
         }
       }
       wave_sync();
-      if (lane < total - r0) {
+      ItemIn in;
+      in.valid = lane < total - r0;
+      int sp = 0, ti = 0, npost = 0;
+      int4 tnb = make_int4(-1, -1, -1, -1);
+      if (in.valid) {
         const int it = L.item[lane];
-        const int Ln = it >> 4, sp = it & 15;
-        const int ti = L.tet[Ln];
-        const int npost = L.npost[lane];
-        const int4 tnb = L.nbr[Ln];
-        const ItemMoves mv = sample_item(rd->key0, rd->key1, cc.window, ti, sp, L.nbar[lane], npost,
-                                         tnb, L.geo[0][Ln], L.geo[1][Ln], L.td[sp]);
+        const int Ln = it >> 4;
+        sp = it & 15;
+        ti = L.tet[Ln];
+        npost = L.npost[lane];
+        tnb = L.nbr[Ln];
+        const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
+        double pr = L.td[sp] * ga.x;
+        if (pr > 1.0) pr = 1.0;
+        in.sp = sp;
+        in.tet = (uint32_t)ti;
+        in.nbar = L.nbar[lane];
+        in.npost = npost;
+        in.p = pr;
+        in.last = last_face(tnb);
+        in.c0 = ga.y;
+        in.c1 = gb.x;
+        in.c2 = gb.y;
+      } else {
+        in.sp = 0;
+        in.tet = 0u;
+        in.nbar = 0.0;
+        in.npost = 0;
+        in.p = 0.0;
+        in.last = 0;
+        in.c0 = in.c1 = in.c2 = 0.0;
+      }
+      const ItemMoves mv = item_round(rd->key0, rd->key1, cc.window, in, L.x);
+      if (in.valid) {
         int32_t* out_s = cc.cout + (size_t)sp * T;
         if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);
         if (mv.o0) atomicAdd(out_s + tnb.x, mv.o0);
         if (mv.o1) atomicAdd(out_s + tnb.y, mv.o1);
         if (mv.o2) atomicAdd(out_s + tnb.z, mv.o2);
         if (mv.o3) atomicAdd(out_s + tnb.w, mv.o3);
-        n_mv += (unsigned long long)(mv.o0 + mv.o1 + mv.o2 + mv.o3);
+        n_mv += (unsigned long long)mv.n;
+        n_fm += (unsigned long long)((mv.o0 != 0) + (mv.o1 != 0) + (mv.o2 != 0) + (mv.o3 != 0));
       }
       wave_sync();  // the round's LDS entries are rebuilt for the next
     }
-    const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv);
+    const unsigned long long ev_sum = wave_sum(n_ev), mv_sum = wave_sum(n_mv), fm_sum = wave_sum(n_fm);
     if (lane == 0) {
       if (ev_sum) atomicAdd(tally_slot(A, cc.run), ev_sum);
       if (mv_sum) atomicAdd(tally_slot(A, cc.run) + 1, mv_sum);
+      if (fm_sum) atomicAdd(tally_slot(A, cc.run) + 2, fm_sum);
     }
     if (errbits) atomicOr(rd->err, errbits);
     wave_sync();  // LDS is rebuilt for the next chunk
@@ -1177,7 +1416,7 @@ __global__ void __launch_bounds__(kBlock) reset_chunks_kernel(const ResetChunk* 
     c.other[j] = 0;
   }
   if (c.begin == 0) {
-    if (threadIdx.x < 2 * kTallySlots) c.tally[threadIdx.x] = 0ull;
+    if (threadIdx.x < kTallyWords * kTallySlots) c.tally[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) *c.err = 0;
   }
 }

@@ -44,7 +44,8 @@ struct alignas(16) RunDesc {
   const uint8_t* region;       // [T] region labels, nullptr when the model has one region
   const double* kcst;          // [8][32] rate constants by region
   const double* lcoef;         // [8][kLStride] listing coefficients by region (alpha, beta[16], gamma[32])
-  unsigned long long* tally;   // [kTallySlots][2] SSA events, molecules moved (summed on read)
+  unsigned long long* tally;   // [kTallySlots][kTallyWords] SSA events, molecules moved, nonzero
+                               // (tet, species, face) moves (summed on read)
   int32_t* err;                // error-flag bits
   int32_t T;
   int32_t n_steps;             // windows of the current sequence (steps 0 .. n_steps-1)
@@ -66,7 +67,7 @@ struct StepArgs {
   int32_t S, R;
   int32_t detect_grid;         // persistent grid of the detect kernel
   int32_t main_grid;           // grid of the main kernel (event blocks + persistent diffusion blocks), >= 2
-  int32_t ev_group_max;        // most queued tiles an event block packs into one chunk (1..8)
+  int32_t ev_group_max;        // most queued tiles an event block takes as one group (1..64)
   int32_t single_run;          // 1: one run, tile t is (run 0, first tet 64 t) without the tile map
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
@@ -93,6 +94,7 @@ constexpr int kQueueStride = 16;  // u64 per counter line
 // b mod kTallySlots), so that blocks finishing together do not queue on one
 // address.
 constexpr int kTallySlots = 64;
+constexpr int kTallyWords = 4;  // SSA events, molecules moved, face moves, unused
 
 // Blocks of the detect and of the main kernel for (S, R) the device holds at
 // once (occupancy x compute units).
@@ -116,7 +118,7 @@ struct ResetChunk {
   const int32_t* src;
   int32_t* dst;
   int32_t* other;
-  unsigned long long* tally;  // [kTallySlots][2]
+  unsigned long long* tally;  // [kTallySlots][kTallyWords]
   int32_t* err;
   int64_t begin, end;
 };

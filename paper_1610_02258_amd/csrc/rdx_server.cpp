@@ -195,13 +195,14 @@ void rdx_server::run_loop() {
       if (rs == RDX_OK && done) {  // a finished request is delivered even if cancelled late
         rs = eng.run_error(&q->run);
         if (rs != RDX_OK) msg = rdx_last_error();
-        unsigned long long tal[2] = {0, 0};
+        unsigned long long tal[3] = {0, 0, 0};
         if (rs == RDX_OK) rs = eng.run_tally(&q->run, tal);
         if (rs == RDX_OK) rs = eng.download_counts(&q->run, q->counts0.data(), false, stream);
         q->stats.windows = q->run.windows_run;
         q->stats.voxel_steps = q->run.voxel_steps;
         q->stats.ssa_events = (int64_t)tal[0];
         q->stats.moves = (int64_t)tal[1];
+        q->stats.face_moves = (int64_t)tal[2];
         q->stats.t = q->run.t;
         q->stats.window_index = q->run.window;
       }

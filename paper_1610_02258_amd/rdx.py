@@ -128,7 +128,8 @@ class _Model(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("windows", C.c_int64), ("voxel_steps", C.c_int64), ("ssa_events", C.c_int64),
-                ("moves", C.c_int64), ("t", C.c_double), ("window_index", C.c_int64)]
+                ("moves", C.c_int64), ("t", C.c_double), ("window_index", C.c_int64),
+                ("face_moves", C.c_int64)]
 
 
 class _ExecOptions(C.Structure):
@@ -169,6 +170,7 @@ class Stats:
     moves: int
     t: float
     window_index: int
+    face_moves: int = 0   # nonzero (tet, species, face) moves
 
 
 def _np_ptr(a):
@@ -359,7 +361,7 @@ class Sim:
     def stats(self, stream=None) -> Stats:
         st = _Stats()
         _check(lib().rdx_get_stats(self._h, C.byref(st), _stream_ptr(stream)), "rdx_get_stats")
-        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index)
+        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index, st.face_moves)
 
     def set_kernel_timing(self, enable: bool):
         _check(lib().rdx_set_kernel_timing(self._h, int(bool(enable))), "rdx_set_kernel_timing")
@@ -510,7 +512,7 @@ class Batch:
     def stats(self, i: int, stream=None) -> Stats:
         st = _Stats()
         _check(lib().rdx_batch_get_stats(self._h, i, C.byref(st), _stream_ptr(stream)), "rdx_batch_get_stats")
-        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index)
+        return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index, st.face_moves)
 
     def set_exec_options(self, autotune: bool = False, fast_grid_div: int = 1, graph_windows: int = 1,
                          event_group: int = 0):
@@ -529,7 +531,7 @@ def _info(ri: _RequestInfo) -> dict:
     return dict(state=REQ_STATES.get(ri.state, ri.state), status=ri.status, n_tets=ri.n_tets,
                 t_submit=ri.t_submit, t_admit=ri.t_admit, t_done=ri.t_done,
                 latency_s=ri.t_done - ri.t_submit,
-                stats=Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index))
+                stats=Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index, st.face_moves))
 
 
 class Server:

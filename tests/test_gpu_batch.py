@@ -55,6 +55,7 @@ def _assert_run(b, i, ref, what):
     st = b.stats(i)
     assert st.ssa_events == ref.tallies.ssa_events, (what, i)
     assert st.moves == ref.tallies.moves, (what, i)
+    assert st.face_moves == ref.tallies.face_moves, (what, i)
     assert st.voxel_steps == ref.tallies.voxel_steps, (what, i)
     assert st.window_index == ref.window and st.t == ref.t, (what, i)
 
@@ -166,6 +167,7 @@ def test_single_sim_with_graphs(rdx, oracle_lib):
         assert np.array_equal(got, ref.counts), n
         st = s.stats()
         assert st.ssa_events == ref.tallies.ssa_events and st.moves == ref.tallies.moves
+        assert st.face_moves == ref.tallies.face_moves
 
 
 def test_set_counts_all_in_one_launch(rdx, oracle_lib):

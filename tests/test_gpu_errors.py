@@ -77,6 +77,6 @@ def test_large_counts_unpacked_path(rdx, oracle_lib):
     got = sim.get_counts()
     assert np.array_equal(got, ref.counts), (got != ref.counts).sum()
     st = sim.stats()
-    assert st.moves == ref.tallies.moves
+    assert st.moves == ref.tallies.moves and st.face_moves == ref.tallies.face_moves
     _say(f"large counts: one window {el * 1e3:.1f} ms, {st.moves} molecules moved")
     sim.close()

@@ -46,6 +46,7 @@ def _assert_same(sim, ref, what=""):
     st = sim.stats()
     assert st.ssa_events == ref.tallies.ssa_events, (what, st.ssa_events, ref.tallies.ssa_events)
     assert st.moves == ref.tallies.moves, (what, st.moves, ref.tallies.moves)
+    assert st.face_moves == ref.tallies.face_moves, (what, st.face_moves, ref.tallies.face_moves)
     assert st.voxel_steps == ref.tallies.voxel_steps
     assert st.window_index == ref.window and st.t == ref.t
 

@@ -160,6 +160,7 @@ def test_random_structure_requests_with_regions(rdx, oracle_lib):
         np.testing.assert_array_equal(got, ref.counts)
         assert info["stats"].ssa_events == ref.tallies.ssa_events
         assert info["stats"].moves == ref.tallies.moves
+        assert info["stats"].face_moves == ref.tallies.face_moves
     srv.close()
 
 

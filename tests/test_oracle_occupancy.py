@@ -159,6 +159,9 @@ def test_cap_with_p1_every_survivor_leaves(oracle_lib):
         assert np.all(out[0, 0::2] == 0)
         q = math.exp(-1.0)
         x = out[0, 1::2]
+        # one nonzero (tet, species, face) move per pair with a survivor
+        assert inst.tallies.face_moves == int((x > 0).sum())
+        assert inst.tallies.moves == int(x.sum())
         obs = np.bincount(x, minlength=N0 + 1)[: N0 + 1]
         assert obs.sum() == n_pairs
         exp = n_pairs * stats.binom.pmf(np.arange(N0 + 1), N0, q)
