@@ -20,22 +20,68 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB_PAR_PATH = os.path.join(HERE, "liboracle_par.so")
 SOURCES = [os.path.join(HERE, "os_oracle.c"), os.path.join(HERE, "rdme_ssa.c")]
+PAR_SOURCES = [os.path.join(HERE, "os_oracle_par.c")]
 
 OS_OK = 0
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, fp contraction off)."""
+    """Compile the oracle with gcc (-O2, fp contraction off), and its all-core
+    build (the same source plus an OpenMP window loop)."""
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu99", "-fPIC", "-shared"]
     if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
-               "-shared", "-o", LIB_PATH + ".tmp", *SOURCES, "-lm"]
-        subprocess.run(cmd, check=True)
+        subprocess.run(["gcc", *flags, "-o", LIB_PATH + ".tmp", *SOURCES, "-lm"], check=True)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    if force or not os.path.exists(LIB_PAR_PATH):
+        subprocess.run(["gcc", *flags, "-fopenmp", f"-I{HERE}", "-o", LIB_PAR_PATH + ".tmp", *PAR_SOURCES,
+                        "-lm"], check=True)
+        os.replace(LIB_PAR_PATH + ".tmp", LIB_PAR_PATH)
     return LIB_PATH
 
 
 _lib = None
+_lib_par = None
+
+
+def _bind(L):
+    p = C.c_void_p
+    L.os_philox4x32_10.argtypes = [p, p, p]
+    L.os_philox4x32_10.restype = None
+    L.os_ln.argtypes = [C.c_double]
+    L.os_ln.restype = C.c_double
+    L.os_build.argtypes = [C.c_int32, p, C.c_int32, p, p, C.c_int32, C.c_int32, C.c_int32,
+                           p, p, p, p, C.c_double, C.POINTER(C.c_void_p)]
+    L.os_build.restype = C.c_int
+    L.os_destroy.argtypes = [p]
+    L.os_destroy.restype = None
+    L.os_get_tau.argtypes = [p]
+    L.os_get_tau.restype = C.c_double
+    L.os_set_rates.argtypes = [p, p]
+    L.os_set_rates.restype = C.c_int
+    L.os_get_geometry.argtypes = [p] * 9
+    L.os_get_geometry.restype = None
+    L.os_run.argtypes = [p, C.c_uint64, p, p, C.c_double, p, p]
+    L.os_run.restype = C.c_int
+    L.os_step.argtypes = [p, C.c_uint64, p, p, C.c_int64, p, p]
+    L.os_step.restype = C.c_int
+    L.os_window_explicit.argtypes = [p, C.c_uint64, p, C.c_double, C.c_int64, p]
+    L.os_window_explicit.restype = C.c_int
+    L.os_sample_binom.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_double,
+                                  C.c_int64, p]
+    L.os_sample_binom.restype = None
+    L.os_sample_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                     C.c_int64, p, p, p]
+    L.os_sample_uniforms.restype = None
+    L.os_ssa_only.argtypes = [p, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, p, p]
+    L.os_ssa_only.restype = C.c_int64
+    if hasattr(L, "rdme_direct"):  # the serial build only
+        for f in (L.rdme_direct, L.rdme_tree):
+            f.argtypes = [C.c_int32, C.c_int32, C.c_int32, p, p, p, p, p, p, p, p, p,
+                          C.c_int32, p, p, C.c_uint64, C.c_int64]
+            f.restype = C.c_int64
+    return L
 
 
 def lib():
@@ -43,42 +89,24 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build(force=True)
-        L = C.CDLL(LIB_PATH)
-        p = C.c_void_p
-        L.os_philox4x32_10.argtypes = [p, p, p]
-        L.os_philox4x32_10.restype = None
-        L.os_ln.argtypes = [C.c_double]
-        L.os_ln.restype = C.c_double
-        L.os_build.argtypes = [C.c_int32, p, C.c_int32, p, p, C.c_int32, C.c_int32, C.c_int32,
-                               p, p, p, p, C.c_double, C.POINTER(C.c_void_p)]
-        L.os_build.restype = C.c_int
-        L.os_destroy.argtypes = [p]
-        L.os_destroy.restype = None
-        L.os_get_tau.argtypes = [p]
-        L.os_get_tau.restype = C.c_double
-        L.os_set_rates.argtypes = [p, p]
-        L.os_set_rates.restype = C.c_int
-        L.os_get_geometry.argtypes = [p] * 9
-        L.os_get_geometry.restype = None
-        L.os_run.argtypes = [p, C.c_uint64, p, p, C.c_double, p, p]
-        L.os_run.restype = C.c_int
-        L.os_step.argtypes = [p, C.c_uint64, p, p, C.c_int64, p, p]
-        L.os_step.restype = C.c_int
-        L.os_window_explicit.argtypes = [p, C.c_uint64, p, C.c_double, C.c_int64, p]
-        L.os_window_explicit.restype = C.c_int
-        L.os_sample_binom.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, C.c_double,
-                                      C.c_int64, p]
-        L.os_sample_binom.restype = None
-        L.os_sample_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
-                                         C.c_int64, p, p, p]
-        L.os_sample_uniforms.restype = None
-        L.os_ssa_only.argtypes = [p, C.c_int32, C.c_double, C.c_uint64, C.c_uint32, p, p]
-        L.os_ssa_only.restype = C.c_int64
-        L.rdme_direct.argtypes = [C.c_int32, C.c_int32, C.c_int32, p, p, p, p, p, p, p, p, p,
-                                  C.c_int32, p, p, C.c_uint64, C.c_int64]
-        L.rdme_direct.restype = C.c_int64
-        _lib = L
+        _lib = _bind(C.CDLL(LIB_PATH))
     return _lib
+
+
+def lib_par():
+    """The all-core build: the serial oracle's functions plus os_step_par."""
+    global _lib_par
+    if _lib_par is None:
+        if not os.path.exists(LIB_PAR_PATH):
+            build(force=True)
+        L = _bind(C.CDLL(LIB_PAR_PATH, mode=C.RTLD_LOCAL))
+        p = C.c_void_p
+        L.os_step_par.argtypes = [p, C.c_uint64, p, p, C.c_int64, p, p, C.c_int]
+        L.os_step_par.restype = C.c_int
+        L.os_max_threads.argtypes = []
+        L.os_max_threads.restype = C.c_int
+        _lib_par = L
+    return _lib_par
 
 
 def _ptr(a: np.ndarray | None):
@@ -138,8 +166,12 @@ class Instance:
     model: dict(D [S], lhs [R,S], rhs [R,S], kcst [n_regions,R])
     """
 
-    def __init__(self, mesh: dict, model: dict, seed: int, tau_override: float = 0.0):
-        L = lib()
+    def __init__(self, mesh: dict, model: dict, seed: int, tau_override: float = 0.0,
+                 parallel: bool = False):
+        # parallel: the handle lives in the all-core build, whose step_parallel
+        # runs the tet loop on several threads (same results bit for bit)
+        L = lib_par() if parallel else lib()
+        self._L = L
         self.verts = np.ascontiguousarray(mesh["verts"], np.float64)
         self.tets = np.ascontiguousarray(mesh["tets"], np.int32)
         reg = mesh.get("region")
@@ -176,7 +208,7 @@ class Instance:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().os_destroy(h)
+            self._L.os_destroy(h)
             self._h = None
 
     def geometry(self) -> dict:
@@ -184,7 +216,7 @@ class Instance:
         out = dict(nbr=np.zeros((T, 4), np.int32), vol=np.zeros(T), area=np.zeros((T, 4)),
                    dist=np.zeros((T, 4)), g=np.zeros((T, 4)), G=np.zeros(T),
                    cum=np.zeros((T, 4)), nav=np.zeros(T))
-        lib().os_get_geometry(self._h, *[_ptr(out[k]) for k in
+        self._L.os_get_geometry(self._h, *[_ptr(out[k]) for k in
                                          ("nbr", "vol", "area", "dist", "g", "G", "cum", "nav")])
         return out
 
@@ -196,7 +228,7 @@ class Instance:
         """Piecewise-constant forcing: new rate constants [n_regions, R] from
         the next window on (the influx of section 3.2 changes every 1 ms)."""
         kc = np.ascontiguousarray(kcst, np.float64).reshape(self.n_regions, self.R)
-        if lib().os_set_rates(self._h, _ptr(kc)) != OS_OK:
+        if self._L.os_set_rates(self._h, _ptr(kc)) != OS_OK:
             raise OracleError(-1, "set_rates: rate constants must be finite and >= 0")
         self.kcst = kc.copy()
 
@@ -230,7 +262,7 @@ class Instance:
         t = C.c_double(self.t)
         w = C.c_int64(self.window)
         tal = _Tallies()
-        st = lib().os_run(self._h, self.seed, _ptr(self.counts), C.byref(t), float(t_end),
+        st = self._L.os_run(self._h, self.seed, _ptr(self.counts), C.byref(t), float(t_end),
                           C.byref(w), C.byref(tal))
         self.t, self.window = t.value, w.value
         self._tally(tal)
@@ -242,7 +274,7 @@ class Instance:
         t = C.c_double(self.t)
         w = C.c_int64(self.window)
         tal = _Tallies()
-        st = lib().os_step(self._h, self.seed, _ptr(self.counts), C.byref(t), int(n_windows),
+        st = self._L.os_step(self._h, self.seed, _ptr(self.counts), C.byref(t), int(n_windows),
                            C.byref(w), C.byref(tal))
         self.t, self.window = t.value, w.value
         self._tally(tal)
@@ -250,9 +282,26 @@ class Instance:
             raise OracleError(st, "step")
         return self.counts
 
+    def step_parallel(self, n_windows: int, threads: int = 0):
+        """As step(), the tet loop on `threads` host threads (0: all); needs
+        parallel=True at construction."""
+        if not hasattr(self._L, "os_step_par"):
+            raise RuntimeError("step_parallel needs Instance(..., parallel=True)")
+        t = C.c_double(self.t)
+        w = C.c_int64(self.window)
+        tal = _Tallies()
+        nt = int(threads) if threads else int(self._L.os_max_threads())
+        st = self._L.os_step_par(self._h, self.seed, _ptr(self.counts), C.byref(t), int(n_windows),
+                                 C.byref(w), C.byref(tal), nt)
+        self.t, self.window = t.value, w.value
+        self._tally(tal)
+        if st != OS_OK:
+            raise OracleError(st, "step_parallel")
+        return self.counts
+
     def window_explicit(self, tau_k: float, window: int):
         tal = _Tallies()
-        st = lib().os_window_explicit(self._h, self.seed, _ptr(self.counts), float(tau_k),
+        st = self._L.os_window_explicit(self._h, self.seed, _ptr(self.counts), float(tau_k),
                                       int(window), C.byref(tal))
         self._tally(tal)
         if st != OS_OK:
@@ -262,23 +311,27 @@ class Instance:
     def ssa_only(self, tet: int, tau_k: float, window: int, N: np.ndarray):
         n = np.ascontiguousarray(N, np.int32).copy()
         nbar = np.zeros(self.S)
-        ev = lib().os_ssa_only(self._h, int(tet), float(tau_k), self.seed, int(window),
+        ev = self._L.os_ssa_only(self._h, int(tet), float(tau_k), self.seed, int(window),
                                _ptr(n), _ptr(nbar))
         return n, nbar, ev
 
 
 def rdme_direct(inst: Instance, counts: np.ndarray, t_rec, seed: int,
-                max_events: int = 10**9) -> np.ndarray:
-    """Exact spatial SSA from ``counts`` (at t=0); returns counts at each time of t_rec."""
+                max_events: int = 10**9, method: str = "direct", return_events: bool = False):
+    """Exact spatial SSA from ``counts`` (at t=0); returns counts at each time of
+    t_rec (and the number of events with return_events).  method "direct"
+    recomputes every channel per event (tiny meshes); "tree" selects through
+    a sum tree of per-tet totals (same law, for timing larger meshes)."""
     geo = inst.geometry()
     c = np.ascontiguousarray(counts, np.int32).reshape(inst.S, inst.T).copy()
     t_rec = np.ascontiguousarray(t_rec, np.float64)
     rec = np.zeros((len(t_rec), inst.S, inst.T), np.int32)
     kc = np.ascontiguousarray(inst.kcst, np.float64)
-    ev = lib().rdme_direct(inst.T, inst.S, inst.R, _ptr(geo["nbr"]), _ptr(geo["g"]),
-                           _ptr(inst.D), _ptr(inst.lhs), _ptr(inst.rhs), _ptr(kc),
-                           _ptr(inst.region), _ptr(geo["nav"]), _ptr(c), len(t_rec),
-                           _ptr(t_rec), _ptr(rec), seed, max_events)
+    fn = {"direct": lib().rdme_direct, "tree": lib().rdme_tree}[method]
+    ev = fn(inst.T, inst.S, inst.R, _ptr(geo["nbr"]), _ptr(geo["g"]),
+            _ptr(inst.D), _ptr(inst.lhs), _ptr(inst.rhs), _ptr(kc),
+            _ptr(inst.region), _ptr(geo["nav"]), _ptr(c), len(t_rec),
+            _ptr(t_rec), _ptr(rec), seed, max_events)
     if ev < 0:
-        raise OracleError(int(ev), "rdme_direct")
-    return rec
+        raise OracleError(int(ev), "rdme_" + method)
+    return (rec, int(ev)) if return_events else rec

@@ -38,6 +38,16 @@ namespace {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------- Philox ----
+// a ^ b ^ k in one VALU instruction, k wave-uniform (an SGPR operand):
+// gfx950's three-input bitwise op with truth table 0x96 (odd parity); the
+// compiler would split the three-way xor into two v_xor_b32.
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// The key (the run's seed) must be the same on every lane of the wave.
 __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2,
                                               uint32_t& x3, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -45,8 +55,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
     // one 32x32->64 multiply each (v_mad_u64_u32)
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
-    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    const uint32_t y0 = xor3_sk((uint32_t)(p1 >> 32), x1, k0);
+    const uint32_t y2 = xor3_sk((uint32_t)(p0 >> 32), x3, k1);
     x0 = y0;
     x1 = (uint32_t)p1;
     x2 = y2;
@@ -509,13 +519,38 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         scale = 1.0;
       }
     }
-    bool f0, f1, f2, fs;
-    th[0] = draw_threshold(scale * it.c0, f0);
-    th[1] = draw_threshold(scale * it.c1, f1);
-    th[2] = draw_threshold(scale * it.c2, f2);
-    th[3] = draw_threshold(scale, fs);
-    full = (f0 || it.last <= 0 ? 1u : 0u) | (f1 || it.last <= 1 ? 2u : 0u) | (f2 || it.last <= 2 ? 4u : 0u) |
-           (fs ? 8u : 0u);
+    w0 = used;
+    nw = (uint32_t)trials;
+    if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
+    if (calls == 1u && !walked) {
+      // the draws lie in one Philox call: this lane makes it, comparing each
+      // uniform w 2^-32 with the item's probabilities as they are
+      const double t0 = scale * it.c0, t1 = scale * it.c1, t2 = scale * it.c2;
+      const uint32_t call = w0 >> 2;
+      uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = it.tet, x3 = window;
+      philox4x32_10(x0, x1, x2, x3, key0, key1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+        const uint32_t idx = 4u * call + (uint32_t)q;
+        const double u = (double)w * 0x1p-32;
+        if (idx >= w0 && idx - w0 < nw && u < scale) {
+          const int f = (0 < it.last && u < t0) ? 0 : ((1 < it.last && u < t1) ? 1 : ((2 < it.last && u < t2) ? 2 : it.last));
+          own += 1u << (8 * f);
+        }
+      }
+      calls = 0u;
+      nw = 0u;
+    }
+    if (calls > 0u || walked) {  // integer thresholds for the words drawn elsewhere
+      bool f0, f1, f2, fs;
+      th[0] = draw_threshold(scale * it.c0, f0);
+      th[1] = draw_threshold(scale * it.c1, f1);
+      th[2] = draw_threshold(scale * it.c2, f2);
+      th[3] = draw_threshold(scale, fs);
+      full = (f0 || it.last <= 0 ? 1u : 0u) | (f1 || it.last <= 1 ? 2u : 0u) | (f2 || it.last <= 2 ? 4u : 0u) |
+             (fs ? 8u : 0u);
+    }
     if (walked) {  // in stream order, after the rounding draw
 #pragma unroll
       for (int k = 0; k < 4; ++k) X.face[k][lane] = 0u;
@@ -527,16 +562,8 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
           ++n;
         }
       }
-      trials = 0;
-    }
-    w0 = used;
-    nw = (uint32_t)trials;
-    if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
-    // an item whose draws lie in one Philox call draws it on its own lane
-    if (calls == 1u) {
-      own = call_leavers(key0, key1, 1u + (uint32_t)it.sp, it.tet, window, w0 >> 2, w0, nw, th[0], th[1], th[2],
-                         th[3], full);
       calls = 0u;
+      nw = 0u;
     }
   }
   // the calls of the other items are shared out over the wave
@@ -938,16 +965,23 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
       // within each class
       int total = 0, errbits = 0;
       const unsigned long long below = (1ull << lane) - 1ull;
+      uint32_t large = 0;  // species of this tet with more than 16 molecules
 #pragma unroll
-      for (int cls = 0; cls < 2; ++cls) {
+      for (int s = 0; s < SMAX; ++s)
+        if (((mask >> s) & 1u) && n_own[s] > kSmallM) large |= 1u << s;
+      const int n_cls = __ballot(large != 0u) ? 2 : 1;  // uniform
+#pragma unroll 1
+      for (int cls = 0; cls < n_cls; ++cls) {
+        const uint32_t cm = n_cls == 1 ? mask : (cls == 0 ? large : mask & ~large);
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
-          const int n = n_own[s];
-          const bool has = ((mask >> s) & 1u) && ((n > kSmallM) == (cls == 0));
+          const bool has = (cm >> s) & 1u;
           const unsigned long long bs = __ballot(has);
-          if (has)  // a count of 2^22 or more does not fit the packed field (0 marks it)
+          if (has) {  // a count of 2^22 or more does not fit the packed field (0 marks it)
+            const int n = n_own[s];
             L.item[total + __popcll(bs & below)] =
                 ((uint32_t)(n < (1 << 22) ? n : 0) << 10) | (uint32_t)(lane << 4) | (uint32_t)s;
+          }
           total += (int)__popcll(bs);
         }
       }
@@ -1423,15 +1457,19 @@ __global__ void __launch_bounds__(kBlock) reset_chunks_kernel(const ResetChunk* 
 __global__ void set_base_kernel(int32_t* base, int32_t value) { *base = value; }
 
 // ----------------------------------------------------------- self-tests ----
-__global__ void selftest_philox_kernel(const uint32_t* in, uint32_t* out, int64_t n) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  uint32_t x0 = in[6 * j], x1 = in[6 * j + 1], x2 = in[6 * j + 2], x3 = in[6 * j + 3];
-  philox4x32_10(x0, x1, x2, x3, in[6 * j + 4], in[6 * j + 5]);
-  out[4 * j] = x0;
-  out[4 * j + 1] = x1;
-  out[4 * j + 2] = x2;
-  out[4 * j + 3] = x3;
+// One vector per wave (block j of 64 lanes), so that its key is wave-uniform
+// as in the window kernels; lane 0 writes.
+__global__ void __launch_bounds__(kWave) selftest_philox_kernel(const uint32_t* in, uint32_t* out) {
+  const int64_t j = blockIdx.x;
+  const cptr<uint32_t> v = as_const(in) + 6 * j;
+  uint32_t x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+  philox4x32_10(x0, x1, x2, x3, v[4], v[5]);
+  if (threadIdx.x == 0) {
+    out[4 * j] = x0;
+    out[4 * j + 1] = x1;
+    out[4 * j + 2] = x2;
+    out[4 * j + 3] = x3;
+  }
 }
 
 __global__ void selftest_ln_kernel(const double* x, double* y, int64_t n) {
@@ -1535,7 +1573,9 @@ hipError_t launch_reset_chunks(const ResetChunk* chunks, int64_t n_chunks, hipSt
 }
 
 hipError_t launch_selftest_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(selftest_philox_kernel, dim3(grid_for(n)), dim3(kBlock), 0, s, in, out, n);
+  if (n <= 0) return hipSuccess;
+  if (n > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(selftest_philox_kernel, dim3((unsigned)n), dim3(kWave), 0, s, in, out);
   return hipGetLastError();
 }
 

@@ -120,3 +120,30 @@ def test_against_exact_spatial_ssa(oracle_lib):
     se = np.sqrt(a.var(0, ddof=1) / runs + b.var(0, ddof=1) / runs)
     z = np.abs(a.mean(0) - b.mean(0)) / se
     assert z.max() < 3.5, z
+
+
+def test_tree_selection_ssa_matches_direct(oracle_lib):
+    """The exact SSA with sum-tree selection (the benchmark's serial-SSA
+    context baseline) has the law of the plain direct method: A + B <-> C
+    with diffusion on a 12-tet mesh, means and variances of the totals and
+    the per-tet mean of A at a fixed time within 3 SE at 1000 runs each."""
+    mesh = I.box_mesh(1, 1, 2, 1e-6, jitter=0.1, seed=6)
+    md = model([1e-12, 0.5e-12, 0.8e-12], [(["A", "B"], ["C"], 4e7), (["C"], ["A", "B"], 5.0)],
+               ["A", "B", "C"])
+    inst = oracle_lib.Instance(mesh.as_dict(), md, 0)
+    t_rec = [20 * inst.tau]
+    runs = 1000
+    a = np.zeros((runs, 3, inst.T))
+    b = np.zeros((runs, 3, inst.T))
+    for r in range(runs):
+        counts = I.place_uniform(mesh, [40, 30, 0], seed=30_000 + r)
+        a[r] = oracle_lib.rdme_direct(inst, counts, t_rec, seed=100 + r)[0]
+        b[r] = oracle_lib.rdme_direct(inst, counts, t_rec, seed=5000 + r, method="tree")[0]
+    ta, tb = a.sum(2), b.sum(2)
+    se = np.sqrt(ta.var(0, ddof=1) / runs + tb.var(0, ddof=1) / runs)
+    assert np.all(np.abs(ta.mean(0) - tb.mean(0)) < 3 * se + 1e-12), (ta.mean(0), tb.mean(0), se)
+    va, vb = ta[:, 2].var(ddof=1), tb[:, 2].var(ddof=1)
+    assert abs(va - vb) < 3 * math.sqrt(2 / (runs - 1)) * max(va, vb)
+    pa, pb = a[:, 0], b[:, 0]
+    z = np.abs(pa.mean(0) - pb.mean(0)) / np.sqrt(pa.var(0, ddof=1) / runs + pb.var(0, ddof=1) / runs)
+    assert z.max() < 3.5, z
