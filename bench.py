@@ -1,30 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of the operator-splitting reaction-diffusion hot path on one GPU.
 
-A step is one complete simulated run of the simple-model workload: a 10 x 10 x
-100 um box of 0.5 um cubes (480,000 jittered tets), 10 species / 12 reactions,
-1e6 molecules, 100 ms simulated = 220 windows (219 of tau, one truncated), every
-window doing the reaction SSA and the diffusion update of every tet.  The
-initial counts are resident in HBM before timing; each step resets the
-simulation to them (device-to-device) and runs to t_end.
+Headline: the dendrite workload -- a seeded random branching tree of tapered
+cylinders voxelised into 996,564 tets, a 15-species / 20-reaction calcium
+buffer model with the calcium influx in 5% of the tets, 50 ms simulated at
+tau = 7.2 us (about 6,950 windows).  A step is one 2.5 ms segment of that run
+(Algorithm 1 to the segment end, the last window of a segment cut there), so
+the default 20 timed steps are the whole 50 ms run, started from counts
+resident in HBM.  Every window does the reaction SSA and the diffusion update
+of every tet.
 
-Prints one JSON line: voxel-steps/s (the value, timed on the production path
-of captured window graphs), SSA events/s and molecules moved/s, the roofline
-of the main window kernel (algorithmic bytes per launch over its average
-launch time from HIP events on the launch stream, taken over a second pass of
-the same steps with per-kernel events), and the oracle timed on host cores on
-a bounded sample of the same workload.
-
-The line also carries, measured after the headline figures, the density and
-refinement series of the same box (``sweep``) and time-varying influx with
-per-region recording on the dendrite workload (``forcing``); ``--no-extra``
-leaves them out.  ``--sweep`` and ``--forcing`` print only that leg.
+Prints one JSON line: voxel-steps/s (the value), SSA events/s, molecules and
+face moves per second; the roofline of the main window kernel (its
+algorithmic bytes per launch over its average launch time from HIP events
+the library records on the launch stream, during the timed region when the
+tuned launch shape uses plain launches, else in a second pass); the oracle
+timed on the host's cores (serially, and its all-core build) on a bounded
+sample of the same run; the exact serial SSA's event rate as the context of
+the paper's speedup over serial SSA.  Secondary legs follow the headline:
+the simple-model box (480,000 tets, 100 ms), the literal 1,296-tet 10 ms run,
+the batched ensemble and the served request stream (each against the plain
+path), the density/refinement series and forcing with recording.
+``--no-extra`` leaves out the series and the forcing leg; ``--sweep``,
+``--forcing`` and ``--simple`` print only that leg.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -32,18 +38,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+SEGMENT_S = 2.5e-3     # simulated time of one timed step of the headline run
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_02258_amd", "csrc", "rdx_kernels.hip")
-COUNTERS = os.path.join(ROOT, "profiles", "window_main_kernel_simple10_counters.txt")
+COUNTERS = {
+    "dendrite_calcium15": os.path.join(ROOT, "profiles", "window_main_kernel_dendrite_counters.txt"),
+    "box20x20x200_simple10": os.path.join(ROOT, "profiles", "window_main_kernel_simple10_counters.txt"),
+}
+TRACES = {
+    "dendrite_calcium15": os.path.join(ROOT, "profiles", "window_kernels_dendrite_kernel_trace.txt"),
+    "box20x20x200_simple10": os.path.join(ROOT, "profiles", "window_kernels_simple10_kernel_trace.txt"),
+}
 
 
-def main_kernel_bytes(T: int, S: int, molecules_moved: float) -> float:
-    """Bytes the main kernel must move in one window: the counts read and the
-    next counts written (8 S per tet), the neighbour ids (16), the couplings
-    G, cum0..cum2 (32), and one 4-byte read-modify-write per moved
-    molecule's target count (8 each; moved molecules bound the nonzero face
-    moves from above).  The listed tets' worklist traffic is left out (a few
-    hundred tets of 480,000)."""
-    return float(T) * (8 * S + 16 + 32) + 8.0 * molecules_moved
+def window_bytes(T: int, S: int, face_moves: float) -> float:
+    """Algorithmic bytes of one window: per tet the counts read and written
+    (8 S), the four neighbour ids (16), the couplings G, cum0..cum2 (32) and
+    N_A V (8); per nonzero (tet, species, face) move one 4-byte
+    read-modify-write of the neighbour's count (8)."""
+    return float(T) * (8 * S + 16 + 32 + 8) + 8.0 * face_moves
 
 
 def detect_kernel_bytes(T: int, S: int, n_regions: int) -> float:
@@ -52,27 +64,63 @@ def detect_kernel_bytes(T: int, S: int, n_regions: int) -> float:
     return float(T) * (4 * S + 8 + (1 if n_regions > 1 else 0))
 
 
-def measured_traffic():
-    """HBM bytes per launch of the main kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
-    calibration factor), or None if the kernel source changed since."""
-    import hashlib
+def _summary(path):
+    """key: value pairs of a committed profile summary, or None if the kernel
+    source changed since it was taken."""
     try:
-        kv = dict(line.split(":", 1) for line in open(COUNTERS) if ":" in line and not line.startswith("#"))
+        kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
         kv = {k.strip(): v.strip() for k, v in kv.items()}
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
-            return None
-        fetch = float(kv["FETCH_SIZE_KiB_per_dispatch"]) * float(kv["fetch_factor"])
-        write = float(kv["WRITE_SIZE_KiB_per_dispatch"]) * float(kv["write_factor"])
-        return (fetch + write) * 1024.0
-    except (OSError, KeyError, ValueError):
+        return kv if kv.get("kernel_source_sha256") == sha else None
+    except OSError:
         return None
 
 
-def cpu_baseline(workload, seconds: float = 12.0) -> dict:
-    """The oracle, single-threaded, on the same mesh/model/seed/counts for as
-    many whole windows as fit in about `seconds`."""
+def measured_traffic(workload: str = "dendrite_calcium15"):
+    """HBM bytes per launch of the main kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by its copy-kernel
+    calibration factor), or None if the kernel source changed since."""
+    kv = _summary(COUNTERS[workload])
+    try:
+        fetch = float(kv["FETCH_SIZE_KiB_per_dispatch"]) * float(kv["fetch_factor"])
+        write = float(kv["WRITE_SIZE_KiB_per_dispatch"]) * float(kv["write_factor"])
+        return (fetch + write) * 1024.0
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def rocprof_durations(workload: str):
+    """Average main / detect kernel durations (us) from the committed
+    rocprofv3 kernel-trace summary, or None if the source changed since."""
+    kv = _summary(TRACES[workload])
+    try:
+        return {"main_us": float(kv["window_main_kernel_avg_us"]),
+                "detect_us": float(kv["window_detect_kernel_avg_us"])}
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def host_info() -> dict:
+    model = platform.processor()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count()
+    return {"nproc": affinity, "cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(workload, seconds: float = 12.0, par_seconds: float = 8.0) -> dict:
+    """The oracle on the same mesh/model/seed/counts: serially for as many
+    whole windows as fit in about `seconds` (the baseline proper), then its
+    all-core build (the same code, the tet loop on every host core the
+    process may use, bit-identical results) for about `par_seconds`."""
     from oracle import oracle as O
 
     inst = O.Instance(workload.mesh.as_dict(), workload.model.as_dict(), workload.seed)
@@ -83,11 +131,232 @@ def cpu_baseline(workload, seconds: float = 12.0) -> dict:
         inst.step(1)
         n += 1
     dt = time.perf_counter() - t0
-    return {"value": inst.tallies.voxel_steps / dt, "unit": "voxel-steps/s", "cores": 1,
-            "kind": "oracle",
+    host = host_info()
+    threads = max(1, min(int(host["nproc"] or 1), 64))
+    par = O.Instance(workload.mesh.as_dict(), workload.model.as_dict(), workload.seed, parallel=True)
+    par.reset(workload.counts)
+    t1 = time.perf_counter()
+    m = 0
+    while time.perf_counter() - t1 < par_seconds:
+        par.step_parallel(1, threads)
+        m += 1
+    dtp = time.perf_counter() - t1
+    return {"value": inst.tallies.voxel_steps / dt, "unit": "voxel-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n} windows of the same run ({n * inst.T} voxel-steps, "
                       f"{inst.tallies.ssa_events} SSA events) in {dt:.1f} s on one host core",
-            "ssa_events_per_s": inst.tallies.ssa_events / dt}
+            "ssa_events_per_s": inst.tallies.ssa_events / dt,
+            "all_cores": {"value": par.tallies.voxel_steps / dtp, "unit": "voxel-steps/s", "cores": threads,
+                          "kind": "oracle, all-core build (bit-identical)",
+                          "sample": f"first {m} windows in {dtp:.1f} s on {threads} threads"},
+            "host": host}
+
+
+def ssa_context(workload, span_s: float, gpu_s_full: float, full_span_s: float) -> dict:
+    """The exact serial SSA (Gillespie's direct method over every reaction and
+    face jump, sum-tree selection) from the same counts for `span_s` of
+    simulated time on one host core: events/s, and the time a serial exact
+    SSA would need for the whole benchmarked span (events extrapolated
+    linearly in simulated time), against the GPU's time for it -- the analogue
+    of the paper's speedup over serial SSA (section 3)."""
+    from oracle import oracle as O
+
+    inst = O.Instance(workload.mesh.as_dict(), workload.model.as_dict(), workload.seed)
+    t0 = time.perf_counter()
+    _, ev = O.rdme_direct(inst, workload.counts, [span_s], seed=workload.seed, method="tree",
+                          return_events=True)
+    dt = time.perf_counter() - t0
+    rate = ev / dt
+    t_ssa_full = ev * (full_span_s / span_s) / rate
+    return {"kind": "exact serial SSA (direct method, sum-tree selection), one host core",
+            "simulated_s": span_s, "events": ev, "seconds": dt, "events_per_s": rate,
+            "extrapolated_full_run_s": t_ssa_full, "gpu_full_run_s": gpu_s_full,
+            "speedup_vs_serial_ssa": t_ssa_full / gpu_s_full}
+
+
+def roofline(T: int, S: int, n_regions: int, windows: int, face_moves: int, kt: dict, source: str,
+             workload: str) -> dict:
+    """Roofline of the main window kernel: the window's algorithmic bytes
+    per launch over its average launch time (HIP events on the launch
+    stream), and the whole window (detect + main) beside it."""
+    n = max(kt["windows"], 1)
+    main_s, det_s = kt["main_ms"] * 1e-3 / n, kt["detect_ms"] * 1e-3 / n
+    b = window_bytes(T, S, face_moves / max(windows, 1))
+    achieved = b / main_s / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload),
+           "kernel": "window_main_kernel", "bytes_per_launch": b,
+           "bytes_per_voxel_step": b / T, "face_moves_per_window": face_moves / max(windows, 1),
+           "avg_launch_us": main_s * 1e6, "duration_source": source,
+           "window": {"detect_us": det_s * 1e6, "main_us": main_s * 1e6,
+                      "achieved_GBs": b / (main_s + det_s) / 1e9,
+                      "frac": b / (main_s + det_s) / 1e9 / HBM_PEAK_GBS},
+           "detect_kernel": {"avg_launch_us": det_s * 1e6,
+                             "bytes_per_launch": detect_kernel_bytes(T, S, n_regions),
+                             "achieved_GBs": detect_kernel_bytes(T, S, n_regions) / det_s / 1e9}}
+    rp = rocprof_durations(workload)
+    if rp:
+        out["rocprof"] = {"main_us": rp["main_us"], "detect_us": rp["detect_us"],
+                          "frac_main": b / (rp["main_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
+def dendrite_headline(steps: int, warmup: int) -> tuple:
+    """The headline: `steps` consecutive segments of SEGMENT_S of one run of
+    the dendrite workload, after `warmup` segments of a first run (the online
+    tuner settles on a launch shape there) and a reset to t = 0."""
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = inputs.config_dendrite()
+    t0 = time.perf_counter()
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    setup_s = time.perf_counter() - t0
+    T, S = sim.T, sim.S
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+    sim.set_exec_options(autotune=True)  # the launch shape is tuned online in the warm-up
+    sim.set_counts(c0, stream=stream)
+    k = 0
+    while k < warmup or (sim.exec_options()["autotune"] and k < warmup + 8):
+        sim.run((k + 1) * SEGMENT_S, stream=stream)
+        torch.cuda.synchronize()
+        k += 1
+    shape = sim.exec_options()
+    in_region = shape["graph_windows"] == 1  # events then cost no change of launch path
+    sim.set_counts(c0, stream=stream)  # t = 0, window 0, tallies cleared
+    sim.kernel_times(reset=True)
+    sim.set_kernel_timing(in_region)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(steps):
+        sim.run((k + 1) * SEGMENT_S, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    st = sim.stats(stream)
+    if in_region:
+        kt = sim.kernel_times(reset=True)
+        source = "HIP events on the launch stream around each kernel, inside the timed region"
+    else:
+        sim.set_kernel_timing(True)
+        sim.set_counts(c0, stream=stream)
+        for k in range(steps):
+            sim.run((k + 1) * SEGMENT_S, stream=stream)
+        torch.cuda.synchronize()
+        kt = sim.kernel_times(reset=True)
+        source = "HIP events on the launch stream around each kernel, second pass of the same steps"
+    sim.set_kernel_timing(False)
+    n_regions = sim.n_regions
+    out = {
+        "value": T * st.windows / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "config": {"workload": w.name, "n_tets": T, "species": S, "reactions": sim.R, "regions": n_regions,
+                   "molecules": int(w.counts.sum()), "t_end_s": steps * SEGMENT_S, "segment_s": SEGMENT_S,
+                   "windows": st.windows, "tau_s": sim.tau, "launch_shape": shape,
+                   "parallelism": "single GPU"},
+        "ssa_events_per_s": st.ssa_events / elapsed,
+        "moves_per_s": st.moves / elapsed,
+        "face_moves_per_s": st.face_moves / elapsed,
+        "setup_s": setup_s,
+        "roofline": roofline(T, S, n_regions, st.windows, st.face_moves, kt, source, w.name),
+    }
+    sim.close()
+    return out, w, elapsed
+
+
+def simple_leg(steps: int, warmup: int) -> dict:
+    """The simple-model box: 10 x 10 x 100 um of 0.5 um cubes (480,000
+    jittered tets), 10 species / 12 reactions, 1e6 molecules, 100 ms = 220
+    windows per step, each step reset from device counts; timed on the
+    production path (captured window graphs when tuned so), kernel durations
+    from a second pass with per-kernel HIP events."""
+    import numpy as np
+    import torch
+    from paper_1610_02258_amd import inputs, rdx
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = inputs.config_simple()
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
+
+    def one():
+        sim.set_counts(c0, stream=stream)
+        sim.run(w.t_end, stream=stream)
+
+    sim.set_exec_options(autotune=True)  # the launch shape is tuned online in the warm-up
+    k = 0
+    while k < warmup or (sim.exec_options()["autotune"] and k < warmup + 8):
+        one()
+        torch.cuda.synchronize()
+        k += 1
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = sim.stats(stream)
+    sim.kernel_times(reset=True)
+    sim.set_kernel_timing(True)
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    kt = sim.kernel_times(reset=True)
+    sim.set_kernel_timing(False)
+    out = {"workload": w.name, "n_tets": sim.T, "t_end_s": w.t_end, "windows_per_step": st.windows,
+           "steps": steps, "voxel_steps_per_s": sim.T * st.windows * steps / el,
+           "ssa_events_per_s": st.ssa_events * steps / el, "ms_per_step": el * 1e3 / steps,
+           "window_us": el * 1e6 / (st.windows * steps), "launch_shape": sim.exec_options(),
+           "roofline": roofline(sim.T, sim.S, sim.n_regions, st.windows, st.face_moves, kt,
+                                "HIP events on the launch stream, second pass of the same steps", w.name)}
+    sim.close()
+    return out, w, el / steps
+
+
+def literal_small_leg(reps: int = 200) -> dict:
+    """The literal small-box run: 1,296 tets, A + B <-> C, 2,000 A and 2,000 B,
+    10 ms = one window cut at t_end; per run on the GPU (reset from device
+    counts + run, enqueued back to back), the oracle, and the exact serial
+    SSA (sum-tree direct method) of the same 10 ms."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1610_02258_amd import inputs, rdx
+
+    stream = torch.cuda.current_stream()
+    w = inputs.config_small()
+    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to("cuda:0")
+    for _ in range(5):
+        sim.set_counts(c0, stream=stream)
+        sim.run(w.t_end, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.set_counts(c0, stream=stream)
+        sim.run(w.t_end, stream=stream)
+    torch.cuda.synchronize()
+    gpu_s = (time.perf_counter() - t0) / reps
+    st = sim.stats(stream)
+    T = sim.T
+    sim.close()
+    ref = O.Instance(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        ref.reset(w.counts)
+        ref.run(w.t_end)
+    ora_s = (time.perf_counter() - t0) / 20
+    t0 = time.perf_counter()
+    ev = 0
+    for r in range(20):
+        _, e = O.rdme_direct(ref, w.counts, [w.t_end], seed=r, method="tree", return_events=True)
+        ev += e
+    ssa_s = (time.perf_counter() - t0) / 20
+    return {"workload": w.name, "n_tets": T, "t_end_s": w.t_end,
+            "windows": st.windows, "gpu_s_per_run": gpu_s, "oracle_s_per_run": ora_s,
+            "exact_ssa_s_per_run": ssa_s, "exact_ssa_events_per_run": ev / 20,
+            "speedup_vs_oracle": ora_s / gpu_s, "speedup_vs_serial_ssa": ssa_s / gpu_s}
 
 
 def batched_leg(steps: int = 2) -> dict:
@@ -266,7 +535,7 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
         sim.set_kernel_timing(False)
         n = max(kt["windows"], 1)
         main_s, det_s = kt["main_ms"] * 1e-3 / n, kt["detect_ms"] * 1e-3 / n
-        b_main = main_kernel_bytes(sim.T, sim.S, st.moves / st.windows)
+        b_main = window_bytes(sim.T, sim.S, st.face_moves / st.windows)
         b_det = detect_kernel_bytes(sim.T, sim.S, w.model.kcst.shape[0])
         rows.append({"workload": w.name, "n_tets": sim.T, "molecules": int(w.counts.sum()),
                      "tau_s": sim.tau, "windows": st.windows,
@@ -411,142 +680,78 @@ def forcing_leg(sim_ms: float = 2.0, record_ms: float = 0.02, force_ms: float = 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20, help="2.5 ms segments of the headline run (20 = 50 ms)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-simple", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline line, print the density and refinement series")
     ap.add_argument("--forcing", action="store_true",
                     help="instead of the headline line, print the forcing and recording measurements")
+    ap.add_argument("--simple", action="store_true",
+                    help="instead of the headline line, print the simple-model leg (steps = its steps)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="leave the density/refinement series and the forcing leg out of the headline line")
+                    help="leave the density/refinement series and the forcing leg out of the line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the workload is a single simulation on one "
               "device (multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
-    from paper_1610_02258_amd import inputs, rdx
+    from paper_1610_02258_amd import rdx
 
     rdx.lib()  # fails loudly if the HIP library is missing
     torch.cuda.init()
-    dev = torch.device("cuda:0")
     if args.sweep:
         print(json.dumps({"sweep": sweep_leg(max(args.steps // 4, 2))}), flush=True)
         return 0
     if args.forcing:
         print(json.dumps({"forcing": forcing_leg()}), flush=True)
         return 0
-    w = inputs.config_simple()
-    t0 = time.perf_counter()
-    sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
-    setup_s = time.perf_counter() - t0
-    T, S = sim.T, sim.S
-    n_regions = w.model.kcst.shape[0]
-    counts0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
-    stream = torch.cuda.current_stream()
-
-    def one_step():
-        sim.set_counts(counts0, stream=stream)
-        sim.run(w.t_end, stream=stream)
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-
-    # timed region: K steps on the production path (windows replayed as
-    # captured HIP graphs).
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        sim.set_counts(counts0, stream=stream)
-        sim.run(w.t_end, stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    # kernel durations: the same steps again with the library recording HIP
-    # events on the launch stream around each window's two kernels (detect
-    # kernel, main kernel).  Events between kernels need plain launches, which
-    # add a few microseconds of launch gaps per window, so this pass is kept
-    # out of the throughput figure above.
-    sim.kernel_times(reset=True)
-    sim.set_kernel_timing(True)
-    torch.cuda.synchronize()
-    t_kt = time.perf_counter()
-    for k in range(args.steps):
-        sim.set_counts(counts0, stream=stream)
-        sim.run(w.t_end, stream=stream)
-    torch.cuda.synchronize()
-    elapsed_timed = time.perf_counter() - t_kt
-    kt = sim.kernel_times(reset=True)
-    sim.set_kernel_timing(False)
-    # tallies of the last step (each step restarts from the same counts)
-    st = sim.stats(stream)
-    windows_per_step = st.windows
-    events_total = st.ssa_events * args.steps
-    moves_total = st.moves * args.steps
-    launches = kt["windows"]
-    avg_main_s = kt["main_ms"] * 1e-3 / max(launches, 1)
-    avg_detect_s = kt["detect_ms"] * 1e-3 / max(launches, 1)
-    voxel_steps = T * windows_per_step * args.steps
-    bytes_main = main_kernel_bytes(T, S, st.moves / windows_per_step)
-    bytes_detect = detect_kernel_bytes(T, S, n_regions)
-    achieved = bytes_main / avg_main_s / 1e9
-    traffic = measured_traffic()
-
-    out = {
-        "metric": "voxel-steps/s & SSA events/s at 1 GPU; batched p50/p99 latency vs plain",
-        "value": voxel_steps / elapsed,
-        "unit": "voxel-steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+i32",
-        "data": "synthetic",
-        "config": {"workload": w.name, "n_tets": T, "species": S, "reactions": sim.R,
-                   "molecules": int(w.counts.sum()), "t_end_s": w.t_end,
-                   "windows_per_step": windows_per_step, "tau_s": sim.tau,
-                   "parallelism": "single GPU"},
-        "ssa_events_per_s": events_total / elapsed,
-        "moves_per_s": moves_total / elapsed,
-        "setup_s": setup_s,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "window_main_kernel", "avg_launch_us": avg_main_s * 1e6,
-                     "bytes_per_launch": bytes_main,
-                     "detect_kernel": {"avg_launch_us": avg_detect_s * 1e6, "bytes_per_launch": bytes_detect,
-                                       "achieved_GBs": bytes_detect / avg_detect_s / 1e9},
-                     "window_us": elapsed * 1e6 / (windows_per_step * args.steps),
-                     "window_us_with_kernel_events": elapsed_timed * 1e6 / (windows_per_step * args.steps),
-                     "window_GBs": (bytes_main + bytes_detect) / (elapsed / (windows_per_step * args.steps)) / 1e9},
-    }
-    sim.close()
+    if args.simple:
+        print(json.dumps({"simple": simple_leg(args.steps, args.warmup)[0]}), flush=True)
+        return 0
+    print("bench: dendrite headline", file=sys.stderr, flush=True)
+    head, w, gpu_s = dendrite_headline(args.steps, args.warmup)
+    out = {"metric": "voxel-steps/s & SSA events/s at 1 GPU; batched p50/p99 latency vs plain",
+           "value": head["value"], "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+i32", "data": "synthetic"}
+    out.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
+    secondary = []
+    if not args.no_simple:
+        secondary.append(("simple", lambda: simple_leg(10, 2)))
+    secondary.append(("literal_small", literal_small_leg))
     if not args.no_batched:
-        print("bench: batched ensemble leg", file=sys.stderr, flush=True)
-        out["batched"] = batched_leg()
+        secondary.append(("batched", batched_leg))
     if not args.no_serve:
-        print("bench: serving leg", file=sys.stderr, flush=True)
-        out["served"] = serve_leg(args.serve_requests)
+        secondary.append(("served", lambda: serve_leg(args.serve_requests)))
     if not args.no_extra:
-        # secondary measurements, outside the timed region; an exception here
-        # is reported in the line rather than losing the headline figures
-        for key, fn in (("sweep", lambda: sweep_leg(2)), ("forcing", forcing_leg)):
-            print(f"bench: {key} leg", file=sys.stderr, flush=True)
-            try:
-                out[key] = fn()
-            except Exception as e:  # noqa: BLE001
-                out[key] = {"error": f"{type(e).__name__}: {e}"}
+        secondary += [("sweep", lambda: sweep_leg(2)), ("forcing", forcing_leg)]
+    simple_w = simple_step_s = None
+    for key, fn in secondary:
+        # measured after the headline; an exception is reported in the line
+        # rather than losing the headline figures
+        print(f"bench: {key} leg", file=sys.stderr, flush=True)
+        try:
+            r = fn()
+            if key == "simple":
+                r, simple_w, simple_step_s = r
+            out[key] = r
+        except Exception as e:  # noqa: BLE001
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        ctx = {"dendrite": ssa_context(w, 2e-7, gpu_s, args.steps * SEGMENT_S)}
+        if simple_w is not None:
+            ctx["simple"] = ssa_context(simple_w, 2e-4, simple_step_s, simple_w.t_end)
+        out["serial_ssa_context"] = ctx
     print(json.dumps(out), flush=True)
     return 0
 

@@ -306,13 +306,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 // the listed tets; the other blocks walk all tiles and do the diffusion of
 // every tet that is not listed (no count changes, the mean occupancy is the
 // count itself).  The serial SSA chains of the few listed tets so run
-// alongside the bandwidth-bound diffusion of the rest instead of after it.
+// alongside the diffusion of the rest instead of after it.
 //
 // Diffusion items: every (tet, species) pair with something to sample becomes
-// an item; a wave-level prefix sum over the lanes' item counts packs them into
-// LDS, and the 64 lanes then walk the packed list.  Moves into the tile's own
-// tets accumulate in LDS and are flushed once, coalesced; the rest are integer
-// atomics into the next count buffer.
+// an item; ballots pack them into LDS (items of more than 16 molecules first,
+// species-major), and they are sampled in rounds of 64 (item_round).  Moves
+// into the tile's own tets accumulate in LDS and are flushed once, coalesced;
+// the rest are integer atomics into the next count buffer.
 constexpr int kWave = 64;
 
 // Tables the window kernels only read -- the run table, the tile map, the
@@ -414,48 +414,66 @@ __device__ __forceinline__ uint32_t draw_threshold(double t, bool& full) {
   return full ? 0xffffffffu : (uint32_t)c;
 }
 
+__device__ __forceinline__ int last_face(int4 nb) {
+  return nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
+}
+
 // One round's item records and per-item face sums.
 struct ItemLds {
-  uint32_t thr[4][kWave];         // thresholds of faces 0-2 and of leaving
-  uint32_t info[kWave];           // bit k: threshold k is 2^32 or more (every draw passes it)
-                                  // or face k is at or after the last face; bits 8-11 species
-  uint32_t tet[kWave];            // run-local tet (the stream's counter)
-  uint32_t w0[kWave];             // first face draw
-  uint32_t nw[kWave];             // face draws
-  unsigned long long off[kWave];  // first call of the item in the round's list of calls
-  uint32_t face[4][kWave];        // leavers by face
-  int slot[kWave];                // item whose calls start at each call of a batch
+  uint32_t info[kWave];     // species (bits 0-3), tet lane (bits 4-9), binomial count (bit 10)
+  uint32_t w0[kWave];       // first face draw
+  uint32_t nw[kWave];       // face draws
+  uint32_t off[kWave];      // first call of the item in the round's list of calls
+  uint32_t face[4][kWave];  // leavers by face
+  int8_t slot[kWave];       // item whose calls start at each call of a batch
+};
+
+// The per-tet arrays a round reads, by tet lane (LDS of the tile or chunk).
+struct ItemView {
+  const int4* nbr;      // neighbours
+  const double2* geo0;  // (G, cum0)
+  const double2* geo1;  // (cum1, cum2)
+  const double* tauD;   // tau_k D_s by species
+  const int* tet;       // run-local tet of each tet lane, or null: base + lane
+  int base;
+  __device__ __forceinline__ uint32_t tet_of(int ln) const { return (uint32_t)(tet ? tet[ln] : base + ln); }
 };
 
 // What a lane brings to a round: its item, or valid == false.
 struct ItemIn {
   bool valid;
-  int sp;          // species
-  uint32_t tet;    // run-local tet index
-  double nbar;     // mean occupancy (the count itself when nothing changed it)
-  int npost;       // count after the reactions
-  double p;        // min(1, tau_k D_s G)
-  int last;        // last face with a neighbour
-  double c0, c1, c2;  // cumulative split fractions
+  int sp;      // species
+  int ln;      // tet lane
+  double nbar; // mean occupancy (the count itself when nothing changed it)
+  int npost;   // count after the reactions
 };
 
-__device__ __forceinline__ unsigned long long wave_scan_add_u64(unsigned long long v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const unsigned long long u = __shfl_up(v, d, kWave);
-    if (lane >= d) v += u;
-  }
+// Inclusive prefix over the 64 lanes with DPP row shifts and row
+// broadcasts (no LDS traffic); `old` is the identity of the operation.
+__device__ __forceinline__ uint32_t wave_scan_add_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
 
-__device__ __forceinline__ int wave_scan_max(int v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int u = __shfl_up(v, d, kWave);
-    if (lane >= d && u > v) v = u;
-  }
+__device__ __forceinline__ int wave_scan_max_dpp(int v) {
+  int t;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false);
+  v = t > v ? t : v;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false);
+  v = t > v ? t : v;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false);
+  v = t > v ? t : v;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false);
+  v = t > v ? t : v;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false);
+  v = t > v ? t : v;
+  t = __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false);
+  v = t > v ? t : v;
   return v;
 }
 
@@ -471,32 +489,41 @@ __device__ __forceinline__ bool draw_leaves(uint32_t w, uint32_t ts, uint32_t fu
   return (full & 8u) != 0u || w < ts;
 }
 
-// Leavers by face of the words [w0, w0 + nw) found in Philox call `call`
-// (words 4 call .. 4 call + 3), a byte per face.
-__device__ __forceinline__ uint32_t call_leavers(uint32_t key0, uint32_t key1, uint32_t stream, uint32_t tet,
-                                                 uint32_t window, uint32_t call, uint32_t w0, uint32_t nw,
-                                                 uint32_t t0, uint32_t t1, uint32_t t2, uint32_t ts,
-                                                 uint32_t full) {
-  uint32_t x0 = call, x1 = stream, x2 = tet, x3 = window;
-  philox4x32_10(x0, x1, x2, x3, key0, key1);
-  uint32_t packed = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
-    const uint32_t idx = 4u * call + (uint32_t)q;
-    if (idx >= w0 && idx - w0 < nw && draw_leaves(w, ts, full)) packed += 1u << (8 * draw_face(w, t0, t1, t2, full));
-  }
-  return packed;
+// The item's leave probability: min(1, tau_k D_s G).
+__device__ __forceinline__ double item_p(const ItemView& V, int sp, int ln) {
+  const double pr = V.tauD[sp] * V.geo0[ln].x;
+  return pr > 1.0 ? 1.0 : pr;
 }
 
-__device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, const ItemIn& it, ItemLds& X) {
+// Integer thresholds of an item's face draws (scale = p, or 1 after a
+// binomial count); `full` bit k: threshold k is never reached (k at or
+// after the last face) or always (2^32), bit 3: every draw leaves.
+__device__ __forceinline__ void item_thresholds(const ItemView& V, int ln, double scale, uint32_t th[4],
+                                                uint32_t& full) {
+  const int last = last_face(V.nbr[ln]);
+  const double2 g0 = V.geo0[ln], g1 = V.geo1[ln];
+  bool f0, f1, f2, fs;
+  th[0] = draw_threshold(scale * g0.y, f0);
+  th[1] = draw_threshold(scale * g1.x, f1);
+  th[2] = draw_threshold(scale * g1.y, f2);
+  th[3] = draw_threshold(scale, fs);
+  full = (f0 || last <= 0 ? 1u : 0u) | (f1 || last <= 1 ? 2u : 0u) | (f2 || last <= 2 ? 4u : 0u) | (fs ? 8u : 0u);
+}
+
+// An item with more face draws than this is walked by its own lane, which
+// keeps a round's calls within 32 bits (only counts of hundreds of millions
+// come near it).
+constexpr uint32_t kMaxSharedCalls = 1u << 24;
+
+__device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, const ItemIn& it,
+                                const ItemView& V, ItemLds& X) {
   const int lane = threadIdx.x;
-  uint32_t w0 = 0, nw = 0, calls = 0, full = 0;
-  uint32_t th[4] = {0u, 0u, 0u, 0u};
+  uint32_t w0 = 0, nw = 0, calls = 0, info = 0;
   uint32_t own = 0;     // leavers by face drawn on this lane, a byte each
   bool walked = false;  // this lane's face counts are in X.face
   if (it.valid) {
-    Draw32 st(key0, key1, 1u + (uint32_t)it.sp, it.tet, window);
+    const uint32_t tet = V.tet_of(it.ln);
+    Draw32 st(key0, key1, 1u + (uint32_t)it.sp, tet, window);
     const double fl = floor(it.nbar);
     const double frac = it.nbar - fl;
     long long m = (long long)fl;
@@ -505,9 +532,10 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
       if (st.u() < frac) m += 1;
       used = 1;
     }
-    const double p = it.p;
+    const double p = item_p(V, it.sp, it.ln);
     double scale = p;
     long long trials = 0;
+    bool binomial = false;
     if (m > 0 && p > 0.0) {
       if (m <= kSmallM) {
         trials = m;
@@ -517,17 +545,21 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         if (p < 1.0) used += (uint32_t)((m + 999) / 1000);
         trials = n > (long long)it.npost ? (long long)it.npost : n;
         scale = 1.0;
+        binomial = true;
       }
     }
     w0 = used;
     nw = (uint32_t)trials;
     if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
+    if (calls > kMaxSharedCalls) walked = true;
     if (calls == 1u && !walked) {
       // the draws lie in one Philox call: this lane makes it, comparing each
       // uniform w 2^-32 with the item's probabilities as they are
-      const double t0 = scale * it.c0, t1 = scale * it.c1, t2 = scale * it.c2;
+      const int last = last_face(V.nbr[it.ln]);
+      const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
+      const double t0 = scale * g0.y, t1 = scale * g1.x, t2 = scale * g1.y;
       const uint32_t call = w0 >> 2;
-      uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = it.tet, x3 = window;
+      uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
       philox4x32_10(x0, x1, x2, x3, key0, key1);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -535,29 +567,22 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         const uint32_t idx = 4u * call + (uint32_t)q;
         const double u = (double)w * 0x1p-32;
         if (idx >= w0 && idx - w0 < nw && u < scale) {
-          const int f = (0 < it.last && u < t0) ? 0 : ((1 < it.last && u < t1) ? 1 : ((2 < it.last && u < t2) ? 2 : it.last));
+          const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
           own += 1u << (8 * f);
         }
       }
       calls = 0u;
       nw = 0u;
     }
-    if (calls > 0u || walked) {  // integer thresholds for the words drawn elsewhere
-      bool f0, f1, f2, fs;
-      th[0] = draw_threshold(scale * it.c0, f0);
-      th[1] = draw_threshold(scale * it.c1, f1);
-      th[2] = draw_threshold(scale * it.c2, f2);
-      th[3] = draw_threshold(scale, fs);
-      full = (f0 || it.last <= 0 ? 1u : 0u) | (f1 || it.last <= 1 ? 2u : 0u) | (f2 || it.last <= 2 ? 4u : 0u) |
-             (fs ? 8u : 0u);
-    }
-    if (walked) {  // in stream order, after the rounding draw
+    if (walked) {  // in stream order, after the rounding draw and the binomial
+      uint32_t th[4], full;
+      item_thresholds(V, it.ln, scale, th, full);
 #pragma unroll
       for (int k = 0; k < 4; ++k) X.face[k][lane] = 0u;
-      int n = 0;
+      long long n = 0;
       for (long long j = 0; j < trials; ++j) {
         const uint32_t w = st.word();
-        if (draw_leaves(w, th[3], full) && n < it.npost) {
+        if (draw_leaves(w, th[3], full) && n < (long long)it.npost) {
           X.face[draw_face(w, th[0], th[1], th[2], full)][lane] += 1u;
           ++n;
         }
@@ -565,21 +590,18 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
       calls = 0u;
       nw = 0u;
     }
+    info = (uint32_t)it.sp | ((uint32_t)it.ln << 4) | (binomial ? 1u << 10 : 0u);
   }
   // the calls of the other items are shared out over the wave
   const bool shared = __ballot(calls > 0u) != 0ull;  // uniform
   if (shared) {
-    const unsigned long long c64 = calls;
-    const unsigned long long incl = wave_scan_add_u64(c64);
-    const unsigned long long first = incl - c64;
-    const unsigned long long total = __shfl(incl, kWave - 1);
+    const uint32_t incl = wave_scan_add_dpp(calls);
+    const uint32_t first = incl - calls;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      X.thr[k][lane] = th[k];
+    for (int k = 0; k < 4; ++k)
       if (!walked) X.face[k][lane] = 0u;
-    }
-    X.info[lane] = full | ((uint32_t)(it.valid ? it.sp : 0) << 8);
-    X.tet[lane] = it.tet;
+    X.info[lane] = info;
     X.w0[lane] = w0;
     X.nw[lane] = nw;
     X.off[lane] = first;
@@ -588,22 +610,34 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
     // calls whose first call is at most b0; the items starting inside the
     // batch mark their first call, and a running maximum over the lanes
     // carries each mark to the calls after it
-    for (unsigned long long b0 = 0; b0 < total; b0 += kWave) {
+    for (uint32_t b0 = 0; b0 < total; b0 += kWave) {
       const unsigned long long held = __ballot(calls > 0u && first <= b0);
       const int i_lo = 63 - __builtin_clzll(held);
       X.slot[lane] = -1;
       wave_sync();
-      if (calls > 0u && first > b0 && first < b0 + kWave) X.slot[(int)(first - b0)] = lane;
+      if (calls > 0u && first > b0 && first - b0 < (uint32_t)kWave) X.slot[first - b0] = (int8_t)lane;
       wave_sync();
       const int v = X.slot[lane];
-      const int item = wave_scan_max(v > i_lo ? v : i_lo);
-      const unsigned long long t = b0 + (unsigned long long)lane;
+      const int item = wave_scan_max_dpp(v > i_lo ? v : i_lo);
+      const uint32_t t = b0 + (uint32_t)lane;
       if (t < total) {
-        const uint32_t iw0 = X.w0[item], info = X.info[item];
-        const uint32_t call = (iw0 >> 2) + (uint32_t)(t - X.off[item]);
-        const uint32_t packed =
-            call_leavers(key0, key1, 1u + ((info >> 8) & 15u), X.tet[item], window, call, iw0, X.nw[item],
-                         X.thr[0][item], X.thr[1][item], X.thr[2][item], X.thr[3][item], info);
+        const uint32_t iw0 = X.w0[item], inf = X.info[item];
+        const int sp = (int)(inf & 15u), ln = (int)((inf >> 4) & 63u);
+        const double scale = (inf >> 10) & 1u ? 1.0 : item_p(V, sp, ln);
+        uint32_t th[4], full;
+        item_thresholds(V, ln, scale, th, full);
+        const uint32_t call = (iw0 >> 2) + (t - X.off[item]);
+        uint32_t x0 = call, x1 = 1u + (uint32_t)sp, x2 = V.tet_of(ln), x3 = window;
+        philox4x32_10(x0, x1, x2, x3, key0, key1);
+        const uint32_t inw = X.nw[item];
+        uint32_t packed = 0;  // leavers of this call by face, a byte each
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+          const uint32_t idx = 4u * call + (uint32_t)q;
+          if (idx >= iw0 && idx - iw0 < inw && draw_leaves(w, th[3], full))
+            packed += 1u << (8 * draw_face(w, th[0], th[1], th[2], full));
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t c = (packed >> (8 * k)) & 0xffu;
@@ -625,10 +659,6 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
     r.n = r.o0 + r.o1 + r.o2 + r.o3;
   }
   return r;
-}
-
-__device__ __forceinline__ int last_face(int4 nb) {
-  return nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
 }
 
 // Tile schedule of a persistent block: the blocks are dispatched round-robin
@@ -995,6 +1025,7 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
       wave_sync();
 
       const int base = cc.base;
+      const ItemView view{L.nbr, L.geo[0], L.geo[1], L.tauD, nullptr, base};
       for (int r0 = 0; r0 < total; r0 += kWave) {
         ItemIn in;
         in.valid = lane < total - r0;
@@ -1007,28 +1038,12 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
           m = (int)(itw >> 10);
           if (m == 0) m = cc.cin[(size_t)sp * T + base + Ln];  // an unpacked large count
           tnb = L.nbr[Ln];
-          const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
-          double pr = L.tauD[sp] * ga.x;
-          if (pr > 1.0) pr = 1.0;
-          in.sp = sp;
-          in.tet = (uint32_t)(base + Ln);
-          in.nbar = (double)m;
-          in.npost = m;
-          in.p = pr;
-          in.last = last_face(tnb);
-          in.c0 = ga.y;
-          in.c1 = gb.x;
-          in.c2 = gb.y;
-        } else {
-          in.sp = 0;
-          in.tet = 0u;
-          in.nbar = 0.0;
-          in.npost = 0;
-          in.p = 0.0;
-          in.last = 0;
-          in.c0 = in.c1 = in.c2 = 0.0;
         }
-        const ItemMoves mv = item_round(key0, key1, cc.window, in, L.x);
+        in.sp = sp;
+        in.ln = Ln;
+        in.nbar = (double)m;
+        in.npost = m;
+        const ItemMoves mv = item_round(key0, key1, cc.window, in, view, L.x);
         if (in.valid) {
           // own remainder and moves to the tile's own tets go to LDS, the
           // rest to the next count buffer
@@ -1260,6 +1275,7 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
     const int incl = wave_inclusive_scan(cnt);
     const int total = __shfl(incl, kWave - 1);
     const int first = incl - cnt;
+    const ItemView view{L.nbr, L.geo[0], L.geo[1], L.td, L.tet, 0};
     // items in rounds of 64: each lane parks the items of the round that
     // are its own, then every lane samples one
     for (int r0 = 0; r0 < total; r0 += kWave) {
@@ -1279,37 +1295,23 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
       wave_sync();
       ItemIn in;
       in.valid = lane < total - r0;
-      int sp = 0, ti = 0, npost = 0;
+      int sp = 0, ti = 0, npost = 0, Ln = 0;
+      double nbar = 0.0;
       int4 tnb = make_int4(-1, -1, -1, -1);
       if (in.valid) {
         const int it = L.item[lane];
-        const int Ln = it >> 4;
+        Ln = it >> 4;
         sp = it & 15;
         ti = L.tet[Ln];
         npost = L.npost[lane];
+        nbar = L.nbar[lane];
         tnb = L.nbr[Ln];
-        const double2 ga = L.geo[0][Ln], gb = L.geo[1][Ln];
-        double pr = L.td[sp] * ga.x;
-        if (pr > 1.0) pr = 1.0;
-        in.sp = sp;
-        in.tet = (uint32_t)ti;
-        in.nbar = L.nbar[lane];
-        in.npost = npost;
-        in.p = pr;
-        in.last = last_face(tnb);
-        in.c0 = ga.y;
-        in.c1 = gb.x;
-        in.c2 = gb.y;
-      } else {
-        in.sp = 0;
-        in.tet = 0u;
-        in.nbar = 0.0;
-        in.npost = 0;
-        in.p = 0.0;
-        in.last = 0;
-        in.c0 = in.c1 = in.c2 = 0.0;
       }
-      const ItemMoves mv = item_round(rd->key0, rd->key1, cc.window, in, L.x);
+      in.sp = sp;
+      in.ln = Ln;
+      in.nbar = nbar;
+      in.npost = npost;
+      const ItemMoves mv = item_round(rd->key0, rd->key1, cc.window, in, view, L.x);
       if (in.valid) {
         int32_t* out_s = cc.cout + (size_t)sp * T;
         if (npost != mv.n) atomicAdd(out_s + ti, npost - mv.n);

@@ -22,13 +22,24 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_algorithmic_bytes_per_launch():
-    # main kernel: counts read + written (8 S), neighbours (16), couplings (32)
-    # per tet, plus 8 per moved molecule
-    assert bench.main_kernel_bytes(480_000, 10, 0.0) == 480_000 * 128
-    assert bench.main_kernel_bytes(1, 1, 3.0) == 56 + 24
+    # one window: counts read + written (8 S), neighbours (16), couplings
+    # (32) and N_A V (8) per tet, plus 8 per nonzero (tet, species, face) move
+    assert bench.window_bytes(996_564, 15, 0.0) == 996_564 * 176
+    assert bench.window_bytes(1, 1, 3.0) == 64 + 24
     # detect kernel: counts (4 S), N_A V (8), region label only with regions
     assert bench.detect_kernel_bytes(480_000, 10, 1) == 480_000 * 48
     assert bench.detect_kernel_bytes(10, 15, 2) == 10 * 69
+
+
+def test_roofline_fields():
+    kt = {"windows": 10, "main_ms": 4.0, "detect_ms": 0.2}
+    r = bench.roofline(1000, 15, 2, 10, 5000, kt, "test", "dendrite_calcium15")
+    b = 1000 * 176 + 8 * 500
+    assert r["bytes_per_launch"] == b
+    assert r["achieved"] == b / 0.4e-3 / 1e9
+    assert r["frac"] == r["achieved"] / 8000.0
+    assert r["window"]["main_us"] == 400.0 and r["window"]["detect_us"] == 20.0
+    assert set(("bound", "achieved", "peak", "unit", "frac", "traffic")) <= set(r)
 
 
 def test_record_kernel_bytes():
@@ -47,8 +58,8 @@ def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
                        "FETCH_SIZE_KiB_per_dispatch: 100\nWRITE_SIZE_KiB_per_dispatch: 50\n"
                        "fetch_factor: 2.0\nwrite_factor: 1.0\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
-    monkeypatch.setattr(bench, "COUNTERS", str(summary))
-    assert bench.measured_traffic() == pytest.approx((100 * 2.0 + 50) * 1024.0)
+    monkeypatch.setattr(bench, "COUNTERS", {"w": str(summary)})
+    assert bench.measured_traffic("w") == pytest.approx((100 * 2.0 + 50) * 1024.0)
     src.write_bytes(b"kernel text, changed")
-    assert bench.measured_traffic() is None
+    assert bench.measured_traffic("w") is None
 

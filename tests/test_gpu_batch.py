@@ -209,7 +209,7 @@ def test_batch_options_validation(rdx):
     with pytest.raises(rdx.RdxError):
         b.set_exec_options(graph_windows=0)
     with pytest.raises(rdx.RdxError):
-        b.set_exec_options(event_group=9)
+        b.set_exec_options(event_group=65)
     b.set_exec_options(fast_grid_div=2, graph_windows=16)
     assert b.exec_options() == dict(autotune=0, fast_grid_div=2, graph_windows=16, event_group=4)
     b.set_exec_options(event_group=2)
@@ -218,7 +218,7 @@ def test_batch_options_validation(rdx):
     b.set_exec_options(autotune=True)
     b.step(300)  # enough windows for every candidate
     o = b.exec_options()
-    assert o["autotune"] == 0 and o["event_group"] in (4, 8) and o["fast_grid_div"] in (1, 2, 4)
+    assert o["autotune"] == 0 and o["event_group"] in (4, 8, 16, 64) and o["fast_grid_div"] in (1, 2, 4)
 
 
 @pytest.mark.parametrize("S,R", [(16, 30), (12, 12)])
