@@ -200,7 +200,16 @@ def roofline(T: int, S: int, n_regions: int, windows: int, face_moves: int, kt: 
     return out
 
 
-def dendrite_headline(steps: int, warmup: int) -> tuple:
+def _apply_shape(sim, shape: str):
+    """Online tuning of the launch shape, or the fixed shape 'div,graph,group'."""
+    if shape:
+        d, g, e = (int(x) for x in shape.split(","))
+        sim.set_exec_options(autotune=False, fast_grid_div=d, graph_windows=g, event_group=e)
+    else:
+        sim.set_exec_options(autotune=True)
+
+
+def dendrite_headline(steps: int, warmup: int, shape: str = "") -> tuple:
     """The headline: `steps` consecutive segments of SEGMENT_S of one run of
     the dendrite workload, after `warmup` segments of a first run (the online
     tuner settles on a launch shape there) and a reset to t = 0."""
@@ -216,7 +225,7 @@ def dendrite_headline(steps: int, warmup: int) -> tuple:
     setup_s = time.perf_counter() - t0
     T, S = sim.T, sim.S
     c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
-    sim.set_exec_options(autotune=True)  # the launch shape is tuned online in the warm-up
+    _apply_shape(sim, shape)  # tuned online in the warm-up unless fixed
     sim.set_counts(c0, stream=stream)
     k = 0
     while k < warmup or (sim.exec_options()["autotune"] and k < warmup + 8):
@@ -265,7 +274,7 @@ def dendrite_headline(steps: int, warmup: int) -> tuple:
     return out, w, elapsed
 
 
-def simple_leg(steps: int, warmup: int) -> dict:
+def simple_leg(steps: int, warmup: int, shape: str = "") -> dict:
     """The simple-model box: 10 x 10 x 100 um of 0.5 um cubes (480,000
     jittered tets), 10 species / 12 reactions, 1e6 molecules, 100 ms = 220
     windows per step, each step reset from device counts; timed on the
@@ -285,7 +294,7 @@ def simple_leg(steps: int, warmup: int) -> dict:
         sim.set_counts(c0, stream=stream)
         sim.run(w.t_end, stream=stream)
 
-    sim.set_exec_options(autotune=True)  # the launch shape is tuned online in the warm-up
+    _apply_shape(sim, shape)  # tuned online in the warm-up unless fixed
     k = 0
     while k < warmup or (sim.exec_options()["autotune"] and k < warmup + 8):
         one()
@@ -694,6 +703,9 @@ def main() -> int:
                     help="instead of the headline line, print the forcing and recording measurements")
     ap.add_argument("--simple", action="store_true",
                     help="instead of the headline line, print the simple-model leg (steps = its steps)")
+    ap.add_argument("--shape", default="",
+                    help="fixed launch shape 'grid_div,graph_windows,event_group' for the headline and the "
+                         "simple leg instead of online tuning (for reproducible profiles)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave the density/refinement series and the forcing leg out of the line")
     args = ap.parse_args()
@@ -714,10 +726,10 @@ def main() -> int:
         print(json.dumps({"forcing": forcing_leg()}), flush=True)
         return 0
     if args.simple:
-        print(json.dumps({"simple": simple_leg(args.steps, args.warmup)[0]}), flush=True)
+        print(json.dumps({"simple": simple_leg(args.steps, args.warmup, args.shape)[0]}), flush=True)
         return 0
     print("bench: dendrite headline", file=sys.stderr, flush=True)
-    head, w, gpu_s = dendrite_headline(args.steps, args.warmup)
+    head, w, gpu_s = dendrite_headline(args.steps, args.warmup, args.shape)
     out = {"metric": "voxel-steps/s & SSA events/s at 1 GPU; batched p50/p99 latency vs plain",
            "value": head["value"], "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
@@ -725,7 +737,7 @@ def main() -> int:
     out.update({k: v for k, v in head.items() if k not in ("value", "ms_per_step")})
     secondary = []
     if not args.no_simple:
-        secondary.append(("simple", lambda: simple_leg(10, 2)))
+        secondary.append(("simple", lambda: simple_leg(10, 2, args.shape)))
     secondary.append(("literal_small", literal_small_leg))
     if not args.no_batched:
         secondary.append(("batched", batched_leg))

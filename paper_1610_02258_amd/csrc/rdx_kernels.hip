@@ -515,6 +515,11 @@ __device__ __forceinline__ void item_thresholds(const ItemView& V, int ln, doubl
 // come near it).
 constexpr uint32_t kMaxSharedCalls = 1u << 24;
 
+// An item with at most this many Philox calls makes them on its own lane;
+// only longer ones (a few species with hundreds of molecules per tet) are
+// shared out, where a lane's walk would hold up the wave.
+constexpr uint32_t kOwnCalls = 4u;
+
 __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, const ItemIn& it,
                                 const ItemView& V, ItemLds& X) {
   const int lane = threadIdx.x;
@@ -552,23 +557,25 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
     nw = (uint32_t)trials;
     if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
     if (calls > kMaxSharedCalls) walked = true;
-    if (calls == 1u && !walked) {
-      // the draws lie in one Philox call: this lane makes it, comparing each
-      // uniform w 2^-32 with the item's probabilities as they are
+    if (calls >= 1u && calls <= kOwnCalls && !walked) {
+      // few Philox calls: this lane makes them, comparing each uniform
+      // w 2^-32 with the item's probabilities as they are (at most 16
+      // draws, so the face counts fit a byte each)
       const int last = last_face(V.nbr[it.ln]);
       const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
       const double t0 = scale * g0.y, t1 = scale * g1.x, t2 = scale * g1.y;
-      const uint32_t call = w0 >> 2;
-      uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
-      philox4x32_10(x0, x1, x2, x3, key0, key1);
+      for (uint32_t call = w0 >> 2; call <= (w0 + nw - 1u) >> 2; ++call) {
+        uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
+        philox4x32_10(x0, x1, x2, x3, key0, key1);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
-        const uint32_t idx = 4u * call + (uint32_t)q;
-        const double u = (double)w * 0x1p-32;
-        if (idx >= w0 && idx - w0 < nw && u < scale) {
-          const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
-          own += 1u << (8 * f);
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+          const uint32_t idx = 4u * call + (uint32_t)q;
+          const double u = (double)w * 0x1p-32;
+          if (idx >= w0 && idx - w0 < nw && u < scale) {
+            const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
+            own += 1u << (8 * f);
+          }
         }
       }
       calls = 0u;
