@@ -250,12 +250,19 @@ rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
  *                  their listed tets packed into chunks of up to 64 lanes
  *                  (1..64; 0 = the default, 4).  Where listed tets are sparse
  *                  (one per tile), larger groups leave fewer, fuller event
- *                  blocks and more blocks for the diffusion of every tet. */
+ *                  blocks and more blocks for the diffusion of every tet.
+ *   event_bins     1: listed tets whose expected events in the window
+ *                  (a0 tau) exceed 1 are queued apart from the others and
+ *                  packed into event chunks of their own, so that a chunk's
+ *                  lanes, which run their SSA chains in lock-step, have
+ *                  chains of similar length (load balancing of skewed event
+ *                  loads, section 3.2); 0: one queue.  Default 1. */
 typedef struct rdx_exec_options {
   int32_t autotune;
   int32_t fast_grid_div;
   int32_t graph_windows;
   int32_t event_group;
+  int32_t event_bins;
 } rdx_exec_options;
 
 rdx_status rdx_set_exec_options(rdx_sim* sim, const rdx_exec_options* opts);
@@ -396,7 +403,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 206
+#define RDX_ABI_VERSION 207
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -234,8 +234,9 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
             dev_alloc(&d_tile_map_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&d_n_tiles_, 1) == hipSuccess && dev_alloc(&d_base_, 1) == hipSuccess &&
             dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
-            dev_alloc(&evq_, (size_t)kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
-            dev_alloc(&evq_count_, (size_t)2 * kQueues * kQueueStride) == hipSuccess && dev_alloc(&wl_tet_, W) == hipSuccess;
+            dev_alloc(&evq_, (size_t)kBins * kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
+            dev_alloc(&evq_count_, (size_t)2 * kBins * kQueues * kQueueStride) == hipSuccess &&
+            dev_alloc(&wl_tet_, W) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
@@ -251,7 +252,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
   RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
-  RDX_HIP(hipMemset(evq_count_, 0, sizeof(unsigned long long) * 2 * kQueues * kQueueStride));
+  RDX_HIP(hipMemset(evq_count_, 0, sizeof(unsigned long long) * 2 * kBins * kQueues * kQueueStride));
   RDX_HIP(hipDeviceSynchronize());
   return RDX_OK;
 }
@@ -481,6 +482,10 @@ rdx_status Engine::plan_steps(Run* r, int64_t n) {
 }
 
 namespace {
+// Threshold of expected events (a0 tau_k) above which a listed tet goes to
+// the heavy bin; with binning off every listed tet is light.
+double heavy_events(const ExecShape& sh) { return sh.event_bins ? 1.0 : HUGE_VAL; }
+
 // Fewest rounds of tiles `resident` blocks need, then the fewest blocks (a
 // multiple of the 8 XCDs) that still finish in that many rounds.
 int rounds_grid(int64_t n_tiles, int resident) {
@@ -613,7 +618,8 @@ rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t s
   const int W = shape_.graph_windows;
   // everything of the arguments that can change between sequences is in the
   // key (pointers and tables are fixed for the engine's life)
-  const long long shape_key = ((long long)a0.main_grid << 40) | ((long long)a0.detect_grid << 8) |
+  const long long shape_key = ((long long)a0.main_grid << 40) | ((long long)a0.detect_grid << 9) |
+                              ((long long)(a0.heavy_events < 1e300 ? 1 : 0) << 8) |
                               ((long long)a0.ev_group_max << 1) | (long long)a0.single_run;
   const auto key = std::make_pair(W, shape_key);
   auto it = graphs_.find(key);
@@ -707,6 +713,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
     grids_for(n_tiles, sh.fast_grid_div, &a.detect_grid, &a.main_grid);
     a.ev_group_max = sh.event_group;
+    a.heavy_events = heavy_events(sh);
     const ExecShape keep = shape_;
     shape_ = sh;
     rdx_status r = RDX_OK;
@@ -725,6 +732,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   if (rec_on_) {  // records between windows: plain launches at the current shape
     grids_for(n_tiles, shape_.fast_grid_div, &a.detect_grid, &a.main_grid);
     a.ev_group_max = shape_.event_group;
+    a.heavy_events = heavy_events(shape_);
     st = launch_plain(a, K, stream);
     if (st != RDX_OK) return st;
     done = K;
@@ -735,6 +743,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
     if (c.graph_windows > 1 && n >= c.graph_windows) {  // capture outside the timed span
       grids_for(n_tiles, c.fast_grid_div, &a.detect_grid, &a.main_grid);
       a.ev_group_max = c.event_group;
+      a.heavy_events = heavy_events(c);
       const ExecShape keep = shape_;
       shape_ = c;
       st = launch_graphs(a, 0, stream);

@@ -82,10 +82,12 @@ struct ExecShape {
   int fast_grid_div = 1;
   int graph_windows = 1;
   int event_group = 4;  // most queued tiles packed into one event chunk
+  int event_bins = 1;   // listed tets binned by expected events (heavy, light)
   bool operator<(const ExecShape& o) const {
     if (fast_grid_div != o.fast_grid_div) return fast_grid_div < o.fast_grid_div;
     if (graph_windows != o.graph_windows) return graph_windows < o.graph_windows;
-    return event_group < o.event_group;
+    if (event_group != o.event_group) return event_group < o.event_group;
+    return event_bins < o.event_bins;
   }
 };
 

@@ -852,24 +852,36 @@ __global__ void __launch_bounds__(kWave) window_detect_kernel(const StepArgs A) 
       const double u = st.oc();
       event = !(1.0 - u > (cc.tau_k * a0) * 1.000001);
     }
-    const unsigned long long ballot = __ballot(event);
+    // binning by expected events: a listed tet with a0 tau_k above the
+    // threshold goes to the heavy bin, the others to the light bin, so that
+    // no event chunk runs light tets in lock-step with a long chain
+    const bool heavy = event && cc.tau_k * a0 > A.heavy_events;
+    const unsigned long long bh = __ballot(heavy), bl = __ballot(event && !heavy);
+    const int nh = (int)__popcll(bh), nl = (int)__popcll(bl);
     if (lane == 0) {
-      A.wl_mask[tile] = ballot;
-      if (ballot) {
-        A.wl_tile_count[tile] = (int)__popcll(ballot);
-        // one atomic on the tile's sub-queue counts the queued tile (low
-        // word) and its listed tets (high word); the old low word is the
-        // tile's slot in that sub-queue
+      A.wl_mask[tile] = bh | bl;
+      if (nh + nl) {
+        A.wl_tile_count[tile] = nh | (nl << 8);
+        // per bin, one atomic on the tile's sub-queue counts the queued tile
+        // (low word) and its listed tets (high word); the old low word is
+        // the tile's slot in that sub-queue
         const int qj = tile & (kQueues - 1);
-        const unsigned long long old =
-            atomicAdd(A.evq_count + ((size_t)(k & 1) * kQueues + qj) * kQueueStride,
-                      ((unsigned long long)__popcll(ballot) << 32) | 1ull);
-        A.evq[(size_t)qj * A.evq_cap + (size_t)(old & 0xffffffffull)] = tile;
+#pragma unroll
+        for (int bin = 0; bin < kBins; ++bin) {
+          const int nb = bin == 0 ? nh : nl;
+          if (nb) {
+            const unsigned long long old = atomicAdd(
+                A.evq_count + (((size_t)(k & 1) * kBins + bin) * kQueues + qj) * kQueueStride,
+                ((unsigned long long)nb << 32) | 1ull);
+            A.evq[((size_t)bin * kQueues + qj) * A.evq_cap + (size_t)(old & 0xffffffffull)] = tile;
+          }
+        }
       }
     }
-    if (event) {  // the tile's listed tets take its own worklist slots
-      const size_t slot = (size_t)tile * kWave + (size_t)__popcll(ballot & ((1ull << lane) - 1ull));
-      A.wl_tet[slot] = i;
+    if (event) {  // the tile's listed tets take its own worklist slots, heavy first
+      const unsigned long long below = (1ull << lane) - 1ull;
+      const int pos = heavy ? (int)__popcll(bh & below) : nh + (int)__popcll(bl & below);
+      A.wl_tet[(size_t)tile * kWave + (size_t)pos] = i;
     }
     cc = nc;
     cur = nxt;
@@ -1342,42 +1354,61 @@ __device__ __forceinline__ void event_chunk(const StepArgs& A, int k, int tile0,
   }
 }
 
-// Event blocks (b of E): groups of K consecutive queue entries, group b,
-// b + E, ...; the listed tets of a group's tiles are packed CW to a chunk
-// (a chunk holds one run), so that tiles with one or two listed tets share
-// one pass of the SSA.
+// The queue of one bin, as the main kernel reassembles it: lane j holds its
+// sub-queue j's inclusive prefix of queued tiles.
+struct BinQueue {
+  int n_queued;  // queued tiles of the bin
+  int K;         // queued tiles per group
+  int n_groups;
+  int q_incl;    // per lane
+};
+
+// Event blocks (b of E): groups of K consecutive queue entries of a bin,
+// group b, b + E, ... over the heavy bin's groups and then the light bin's;
+// the listed tets of a group's tiles are packed CW to a chunk (a chunk holds
+// one run and one bin), so that tiles with one or two listed tets share one
+// pass of the SSA, and tets expected to have several events share chunks
+// with each other only.
 template <int SMAX, int RMAX>
-__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, int n_queued, int K,
-                                           int q_incl, EventLds<SMAX, RMAX>& L) {
+__device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int E, const BinQueue* Q,
+                                           EventLds<SMAX, RMAX>& L) {
   constexpr int CW = EventLds<SMAX, RMAX>::CW;
   const int lane = threadIdx.x;
   bool tables = false;
   int cache_run = -1;
   uint32_t dmask = 0;  // species with tau_k D_s > 0 in the cached run
   const cptr<int> tile_run = as_const(reinterpret_cast<const int*>(A.tile_map));
-  const int n_groups = (n_queued + K - 1) / K;
+  const int n_groups = Q[0].n_groups + Q[1].n_groups;
 
-  for (int g = b; g < n_groups; g += E) {
+  for (int gg = b; gg < n_groups; gg += E) {
+    const int bin = gg < Q[0].n_groups ? 0 : 1;
+    const BinQueue& B = Q[bin];
+    const int g = gg - (bin ? Q[0].n_groups : 0);
+    const int* evq = A.evq + (size_t)bin * kQueues * A.evq_cap;
     // the group's tiles, listed counts and runs: lane j loads entry j (one
     // round of loads for the whole group)
-    const int q0 = g * K;
-    const int nq = n_queued - q0 < K ? n_queued - q0 : K;
+    const int q0 = g * B.K;
+    const int nq = B.n_queued - q0 < B.K ? B.n_queued - q0 : B.K;
     // entry q is slot q - (tiles of the sub-queues before j) of sub-queue j,
     // j the first sub-queue whose inclusive prefix exceeds q
-    int g_tile = 0, g_n = 0, g_run = -1;
+    int g_tile = 0, g_n = 0, g_first = 0, g_run = -1;
     for (int l = 0; l < nq; ++l) {
       const int q = q0 + l;
-      const int j = (int)__popcll(__ballot(q_incl <= q));
-      const int before = j > 0 ? __builtin_amdgcn_readlane(q_incl, j - 1) : 0;
-      if (lane == l) g_tile = A.evq[(size_t)j * A.evq_cap + (size_t)(q - before)];
+      const int j = (int)__popcll(__ballot(B.q_incl <= q));
+      const int before = j > 0 ? __builtin_amdgcn_readlane(B.q_incl, j - 1) : 0;
+      if (lane == l) g_tile = evq[(size_t)j * A.evq_cap + (size_t)(q - before)];
     }
     if (lane < nq) {
-      g_n = A.wl_tile_count[g_tile];
+      // the bin's listed tets of the tile and their first worklist slot
+      // (heavy tets first)
+      const int c = A.wl_tile_count[g_tile];
+      g_n = bin == 0 ? (c & 0xff) : (c >> 8);
+      g_first = bin == 0 ? 0 : (c & 0xff);
       g_run = A.single_run ? 0 : tile_run[2 * g_tile];
     }
     // walk the group's tiles and their listed tets in order; the chunk is
     // run from one place in the code
-    int q = -1, tile = 0, n = 0, run = -1, j0 = 0;
+    int q = -1, tile = 0, n = 0, first = 0, run = -1, j0 = 0;
     int fill = 0, tile0 = 0, run0 = -1;
     size_t slot = 0;
     for (;;) {
@@ -1390,6 +1421,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
         }
         if (q < nq) {
           tile = __builtin_amdgcn_readlane(g_tile, q);
+          first = __builtin_amdgcn_readlane(g_first, q);
           run = __builtin_amdgcn_readlane(g_run, q);
         }
       }
@@ -1404,7 +1436,7 @@ __device__ __forceinline__ void event_part(const StepArgs& A, int k, int b, int 
         run0 = run;
       }
       const int take = n - j0 < CW - fill ? n - j0 : CW - fill;
-      if (lane >= fill && lane < fill + take) slot = (size_t)tile * kWave + (size_t)(j0 + lane - fill);
+      if (lane >= fill && lane < fill + take) slot = (size_t)tile * kWave + (size_t)(first + j0 + lane - fill);
       fill += take;
       j0 += take;
     }
@@ -1419,33 +1451,40 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3)))
 window_main_kernel(const StepArgs A) {
   __shared__ MainLds<SMAX, RMAX> lds;
   const int k = step_index(A);
-  // the sub-queues: lane j holds sub-queue j's tiles and their inclusive
-  // prefix sum over the sub-queues
+  // the sub-queues of each bin: lane j holds sub-queue j's tiles and their
+  // inclusive prefix sum over the sub-queues
   const int lane = threadIdx.x;
-  const unsigned long long qc = A.evq_count[((size_t)(k & 1) * kQueues + lane) * kQueueStride];
-  const int q_n = (int)(qc & 0xffffffffull);
-  const int q_incl = wave_scan_add(q_n);
-  const int n_queued = __builtin_amdgcn_readlane(q_incl, kWave - 1);
-  const int n_listed = __builtin_amdgcn_readlane(wave_scan_add((int)(qc >> 32)), kWave - 1);
-  if (blockIdx.x == 0)  // the next window's queue starts empty
-    A.evq_count[((size_t)((k + 1) & 1) * kQueues + lane) * kQueueStride] = 0;
-  // event blocks: one per group of K queued tiles, K chosen so that a group
-  // lists about 64 tets, at most ev_group_max tiles (a launch-shape setting:
-  // longer groups can make the event blocks the last to finish); a multiple
-  // of the 8 XCDs (so that the diffusion blocks keep their XCD mapping), at
-  // most half the grid
   const int G = gridDim.x;
-  int E = 0, K = 1;
-  if (n_queued > 0) {
-    K = n_listed > 0 ? (int)((64ll * n_queued) / n_listed) : 1;
-    const int K_max = A.ev_group_max >= 1 ? A.ev_group_max : 1;
+  const int K_max = A.ev_group_max >= 1 ? A.ev_group_max : 1;
+  BinQueue Q[kBins];
+  int n_groups = 0;
+#pragma unroll
+  for (int bin = 0; bin < kBins; ++bin) {
+    const size_t at = (((size_t)(k & 1) * kBins + bin) * kQueues + lane) * kQueueStride;
+    const unsigned long long qc = A.evq_count[at];
+    Q[bin].q_incl = wave_scan_add((int)(qc & 0xffffffffull));
+    Q[bin].n_queued = __builtin_amdgcn_readlane(Q[bin].q_incl, kWave - 1);
+    const int n_listed = __builtin_amdgcn_readlane(wave_scan_add((int)(qc >> 32)), kWave - 1);
+    // one group of K queued tiles per event block, K chosen so that a group
+    // lists about 64 tets, at most ev_group_max tiles (a launch-shape
+    // setting: longer groups can make the event blocks the last to finish)
+    int K = n_listed > 0 ? (int)((64ll * Q[bin].n_queued) / n_listed) : 1;
     K = K < 1 ? 1 : (K > K_max ? K_max : K);
-    const int n_groups = (n_queued + K - 1) / K;
+    Q[bin].K = K;
+    Q[bin].n_groups = (Q[bin].n_queued + K - 1) / K;
+    n_groups += Q[bin].n_groups;
+    if (blockIdx.x == 0)  // the next window's queue starts empty
+      A.evq_count[(((size_t)((k + 1) & 1) * kBins + bin) * kQueues + lane) * kQueueStride] = 0;
+  }
+  // event blocks: one per group, a multiple of the 8 XCDs (so that the
+  // diffusion blocks keep their XCD mapping), at most half the grid
+  int E = 0;
+  if (n_groups > 0) {
     const int cap = G / 2 >= 8 ? (G / 2) & ~7 : (G / 2 > 0 ? G / 2 : 1);
     E = (n_groups + 7) & ~7;
     if (E > cap) E = cap;
   }
-  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, n_queued, K, q_incl, lds.e);
+  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, Q, lds.e);
   else diffusion_part<SMAX, RMAX>(A, k, (int)blockIdx.x - E, G - E, lds.d);
 }
 

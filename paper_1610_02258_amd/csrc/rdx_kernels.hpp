@@ -68,6 +68,7 @@ struct StepArgs {
   int32_t detect_grid;         // persistent grid of the detect kernel
   int32_t main_grid;           // grid of the main kernel (event blocks + persistent diffusion blocks), >= 2
   int32_t ev_group_max;        // most queued tiles an event block takes as one group (1..64)
+  double heavy_events;         // a listed tet with a0 tau_k above this goes to the heavy bin
   int32_t single_run;          // 1: one run, tile t is (run 0, first tet 64 t) without the tile map
   const DevModel* model;
   int32_t info[32];            // = model->info, in kernel arguments for scalar loads
@@ -77,17 +78,21 @@ struct StepArgs {
   // entries of tile t are slots 64 t .. 64 t + wl_tile_count[t] - 1
   unsigned long long* wl_mask; // [tiles] listed tets of each tile (bit = lane)
   int32_t* wl_tile_count;      // [tiles], valid for the tiles in the queue
-  // queue of the tiles with listed tets, in kQueues sub-queues (tile t goes
-  // to sub-queue t mod kQueues, slots q * evq_cap ...) so that no counter is
-  // contended by every tile
-  int32_t* evq;                // [kQueues][evq_cap]
+  // queues of the tiles with listed tets, one per bin (heavy: tets expected
+  // to have more than heavy_events events; light: the others), each in
+  // kQueues sub-queues (tile t goes to sub-queue t mod kQueues, slots
+  // q * evq_cap ...) so that no counter is contended by every tile; a tile's
+  // listed tets take its worklist slots heavy first, wl_tile_count[t] =
+  // heavy | light << 8
+  int32_t* evq;                // [kBins][kQueues][evq_cap]
   int32_t evq_cap;
-  unsigned long long* evq_count;  // [2][kQueues][16] by step parity, one 128-byte line per counter:
-                                  // queued tiles (low word), their listed tets (high word)
+  unsigned long long* evq_count;  // [2][kBins][kQueues][16] by step parity, one 128-byte line per
+                                  // counter: queued tiles (low word), their listed tets (high word)
   int32_t* wl_tet;
 };
 
 constexpr int kQueues = 64;
+constexpr int kBins = 2;  // heavy, light
 constexpr int kQueueStride = 16;  // u64 per counter line
 
 // Tallies are spread over this many slots per run (block b adds to slot

@@ -210,10 +210,13 @@ def test_batch_options_validation(rdx):
         b.set_exec_options(graph_windows=0)
     with pytest.raises(rdx.RdxError):
         b.set_exec_options(event_group=65)
+    with pytest.raises(rdx.RdxError):
+        b.set_exec_options(event_bins=2)
     b.set_exec_options(fast_grid_div=2, graph_windows=16)
-    assert b.exec_options() == dict(autotune=0, fast_grid_div=2, graph_windows=16, event_group=4)
-    b.set_exec_options(event_group=2)
-    assert b.exec_options()["event_group"] == 2
+    assert b.exec_options() == dict(autotune=0, fast_grid_div=2, graph_windows=16, event_group=4,
+                                    event_bins=1)
+    b.set_exec_options(event_group=2, event_bins=0)
+    assert b.exec_options()["event_group"] == 2 and b.exec_options()["event_bins"] == 0
     # the tuner's choice is one of its candidates and is kept once tuning ends
     b.set_exec_options(autotune=True)
     b.step(300)  # enough windows for every candidate

@@ -255,14 +255,17 @@ def test_density_and_refinement_series(rdx, oracle_lib, density, h, extent):
         _assert_same(sim, ref, f"window {k}")
 
 
-@pytest.mark.parametrize("density,h", [(10.0, 0.5), (1.0, 0.25)])
-def test_series_full_size_prefix(rdx, oracle_lib, density, h):
+@pytest.mark.parametrize("density,h,bins", [(10.0, 0.5, 1), (10.0, 0.5, 0), (1.0, 0.25, 1)])
+def test_series_full_size_prefix(rdx, oracle_lib, density, h, bins):
     """The series at full size: 480,000 tets with 1e7 molecules (10x the
-    benchmarked density) and the refined 3,840,000-tet box (0.25 um cubes):
-    the first windows compared on every count."""
+    benchmarked density, with the listed tets binned by expected events and
+    in one queue) and the refined 3,840,000-tet box (0.25 um cubes): the
+    first windows compared on every count."""
     w = I.config_simple_variant(density, h)
-    _say(f"case: {w.name}, T={w.mesh.n_tets}")
+    _say(f"case: {w.name}, T={w.mesh.n_tets}, event bins {bins}")
     sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    sim.set_exec_options(autotune=False, fast_grid_div=1, graph_windows=1, event_group=8,
+                         event_bins=bins)
     for k in range(2):
         sim.step(1)
         ref.step(1)
