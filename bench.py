@@ -477,6 +477,23 @@ def serve_leg(n_requests: int = 400, rate: float = 200.0, submit_threads: int = 
     sst = srv.stats()
     srv.close()
 
+    # the same requests all at once: the server's throughput when it is never
+    # short of work
+    srv = rdx.Server(model, hbm_budget_bytes=16 << 30, tick_windows=8)
+    t0 = time.perf_counter()
+
+    def submit_now(j):
+        w = reqs[j][1]
+        return srv.submit(mesh_d[id(w.mesh)], model, w.seed, w.counts, w.t_end)
+
+    with cf.ThreadPoolExecutor(submit_threads) as pool:
+        tickets = list(pool.map(submit_now, range(len(reqs))))
+    for tk in tickets:
+        srv.wait(tk)
+    burst_s = time.perf_counter() - t0
+    bst = srv.stats()
+    srv.close()
+
     # plain FIFO
     lat_p = []
     t0 = time.perf_counter()
@@ -497,7 +514,11 @@ def serve_leg(n_requests: int = 400, rate: float = 200.0, submit_threads: int = 
             "plain_p50_s": pct(lat_p, 50), "plain_p99_s": pct(lat_p, 99),
             "served_voxel_steps_per_s": vs / makespan_s, "plain_voxel_steps_per_s": vs / makespan_p,
             "served_makespan_s": makespan_s, "plain_makespan_s": makespan_p,
-            "server_ticks": sst["ticks"], "server_busy_s": sst["busy_s"],
+            "server_ticks": sst["ticks"], "server_device_busy_s": sst["busy_s"],
+            "server_device_busy_frac": sst["busy_s"] / makespan_s, "server_worker_s": sst["worker_s"],
+            "burst_voxel_steps_per_s": vs / burst_s, "burst_makespan_s": burst_s,
+            "burst_device_busy_frac": bst["busy_s"] / burst_s, "burst_ticks": bst["ticks"],
+            "burst_worker_s": bst["worker_s"],
             "submit_threads": submit_threads}
 
 

@@ -109,7 +109,10 @@ typedef struct rdx_sim rdx_sim;
 rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t seed,
                       double tau_override, rdx_sim** out);
 
-/* Releases all host and device memory of the simulation (NULL is ignored). */
+/* Releases all host and device memory of the simulation (NULL is ignored),
+ * after waiting for the work the simulation's calls enqueued on each stream
+ * (it does not synchronise the whole device, so it may run while another
+ * thread captures a graph). */
 void rdx_destroy(rdx_sim* sim);
 
 /* Initial populations (section 2.1, last step): counts [n_species*n_tets].
@@ -174,7 +177,9 @@ rdx_status rdx_region_counts(rdx_sim* sim, int64_t* out, int is_device_ptr, void
  * Every call on one GPU shares that array and fully rewrites the part it
  * reads, so nothing needs clearing, but calls that overlap in time on one
  * GPU (different streams, or different host threads without ordering) race
- * on it: order them on one stream.  Sizes: any n_tets; the slots needed for
+ * on it: order them on one stream.  The call records nothing on `stream`
+ * for rdx_destroy to wait on: destroy the simulation only once `stream` has
+ * reached the call.  Sizes: any n_tets; the slots needed for
  * (n_tets, n_species) are checked against the array.
  * Errors: RDX_EINVAL (null handle or out, or more scratch than the array
  * holds), RDX_EHIP. */
@@ -324,12 +329,15 @@ rdx_status rdx_batch_get_exec_options(const rdx_batch* batch, rdx_exec_options* 
  *
  * A server owns a device-memory budget and one worker thread.  Each submitted
  * request (mesh, model parameters, seed, initial counts, t_end) is validated
- * and set up (section 2.1) on the submitting thread, then queued.  Between
- * scheduling ticks the worker admits queued requests in arrival order while
- * the budget has room for their device state, runs one tick -- up to
- * tick_windows windows of every resident request, in the same launches -- and
- * retires requests that reached t_end, releasing their memory for the next
- * admissions.  A request's result is bit-identical to the same simulation run
+ * and set up (section 2.1) on the submitting thread, then queued.  The
+ * worker admits queued requests in arrival order while the budget has room
+ * for their device state, enqueues one tick -- up to tick_windows windows of
+ * every resident request, in the same launches -- and retires requests that
+ * reached t_end, releasing their memory for the next admissions.  The ticks
+ * are pipelined: uploads of new requests and reads of finished ones go on a
+ * second stream while the tick before runs, and the worker waits for a
+ * tick's end only to retire what it finished, after the next tick is already
+ * enqueued.  A request's result is bit-identical to the same simulation run
  * alone (rdx_create, rdx_set_counts, rdx_run(t_end)).  Latency is measured
  * from submission to retirement.
  *
@@ -369,11 +377,14 @@ typedef struct rdx_request_info {
 typedef struct rdx_server_stats {
   int64_t submitted, completed, failed, cancelled, queued, running, ticks;
   int64_t voxel_steps, ssa_events, moves;  /* summed over completed requests */
-  double busy_s;            /* worker time spent in ticks */
+  double busy_s;            /* device time of the ticks: from each tick's first to its last
+                               launch on the device (HIP events), summed over retired ticks */
   double uptime_s;
   double latency_p50_s;     /* nearest-rank quantiles of completion - submission */
   double latency_p99_s;
   int64_t capacity_tets;    /* worklist capacity derived from the budget */
+  double worker_s;          /* worker thread time spent on admissions' uploads and on planning
+                               and enqueueing ticks (not on waiting for the device) */
 } rdx_server_stats;
 
 /* Errors: RDX_EINVAL (bad structure or options), RDX_ENOMEM, RDX_EHIP. */
@@ -403,7 +414,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 207
+#define RDX_ABI_VERSION 208
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

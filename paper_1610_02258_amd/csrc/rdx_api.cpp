@@ -168,7 +168,7 @@ rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t see
   s->run.seed = seed;
   (void)hipGetDevice(&s->device);
   st = s->eng.init(s->run.host, Engine::run_bytes(s->run.host), 1, s->run.host.T);
-  if (st == RDX_OK) st = s->eng.add_run(&s->run, nullptr);
+  if (st == RDX_OK) st = s->eng.add_run(&s->run, s->eng.own_stream());
   if (st != RDX_OK) {
     const std::string msg = rdx_last_error();
     delete s;
@@ -181,7 +181,7 @@ rdx_status rdx_create(const rdx_mesh* mesh, const rdx_model* model, uint64_t see
 void rdx_destroy(rdx_sim* s) {
   if (!s) return;
   (void)hipSetDevice(s->device);
-  (void)hipDeviceSynchronize();
+  s->eng.drain();  // every stream the simulation used, not the whole device
   if (s->rec) (void)hipFree(s->rec);
   delete s;
 }
@@ -213,7 +213,7 @@ rdx_status rdx_region_counts_static(rdx_sim* s, int64_t* out, void* stream) {
     return set_error(RDX_EINVAL, "the region sums need " + std::to_string(need) + " bytes of scratch, more than the " +
                                      std::to_string(cap) + "-byte static array");
   return s->eng.region_counts(&s->run, scratch, reinterpret_cast<unsigned long long*>(out),
-                              reinterpret_cast<hipStream_t>(stream));
+                              reinterpret_cast<hipStream_t>(stream), false);
 }
 
 rdx_status rdx_set_counts(rdx_sim* s, const int32_t* counts, int is_device_ptr, void* stream) {
@@ -442,8 +442,9 @@ rdx_status rdx_load(rdx_sim* s, const void* buf, size_t len, void* stream) {
   if (st != RDX_OK) return st;
   unsigned long long tal[3] = {(unsigned long long)h.events, (unsigned long long)h.moves,
                                (unsigned long long)h.face_moves};
-  RDX_HIP(hipStreamSynchronize(strm));  // the tallies were cleared on this stream
-  RDX_HIP(hipMemcpy(r.tally, tal, sizeof tal, hipMemcpyHostToDevice));  // into slot 0
+  // into slot 0, behind the clearing of the tallies on the same stream
+  RDX_HIP(hipMemcpyAsync(r.tally, tal, sizeof tal, hipMemcpyHostToDevice, strm));
+  RDX_HIP(hipStreamSynchronize(strm));
   r.t = h.t;
   r.windows_run = h.windows_run;
   r.voxel_steps = h.voxel_steps;
@@ -480,7 +481,8 @@ rdx_status rdx_batch_create(int32_t n_runs, const rdx_mesh* meshes, const rdx_mo
   }
   (void)hipGetDevice(&b->device);
   rdx_status st = b->eng.init(b->runs[0].host, bytes, n_runs, tets);
-  for (int32_t i = 0; st == RDX_OK && i < n_runs; ++i) st = b->eng.add_run(&b->runs[(size_t)i], nullptr);
+  for (int32_t i = 0; st == RDX_OK && i < n_runs; ++i)
+    st = b->eng.add_run(&b->runs[(size_t)i], b->eng.own_stream());
   if (st != RDX_OK) {
     const std::string msg = rdx_last_error();
     delete b;
@@ -494,7 +496,7 @@ rdx_status rdx_batch_create(int32_t n_runs, const rdx_mesh* meshes, const rdx_mo
 void rdx_batch_destroy(rdx_batch* b) {
   if (!b) return;
   (void)hipSetDevice(b->device);
-  (void)hipDeviceSynchronize();
+  b->eng.drain();
   if (b->rec) (void)hipFree(b->rec);
   delete b;
 }

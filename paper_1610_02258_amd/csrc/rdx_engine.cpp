@@ -184,10 +184,45 @@ size_t Engine::worklist_bytes_per_tet(int S) {
   return 4 + 1;  // the tet index of its slot, and its share of the per-tile count and queue entry
 }
 
+void Engine::fence(hipStream_t stream) {
+  for (auto& f : fences_)
+    if (f.first == stream) {
+      (void)hipEventRecord(f.second, stream);
+      return;
+    }
+  hipEvent_t ev = nullptr;
+  if (fences_.size() >= 16 || hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamSynchronize(stream);  // too many streams: wait for this one now
+    return;
+  }
+  (void)hipEventRecord(ev, stream);
+  fences_.emplace_back(stream, ev);
+}
+
+void Engine::drain() {
+  for (auto& f : fences_) {
+    (void)hipEventSynchronize(f.second);
+    (void)hipEventDestroy(f.second);
+  }
+  fences_.clear();
+}
+
+namespace {
+// Marks `stream` in the engine's fences when the enclosing method returns,
+// whatever it enqueued before an early error return.
+struct FenceOnExit {
+  Engine* e;
+  hipStream_t s;
+  ~FenceOnExit() { e->fence(s); }
+};
+}  // namespace
+
 Engine::~Engine() {
+  drain();
   if (staged_) (void)hipEventSynchronize(staged_);
   free_graphs();
   if (capture_stream_) (void)hipStreamDestroy(capture_stream_);
+  if (own_) (void)hipStreamDestroy(own_);
   for (hipEvent_t e : marks_) (void)hipEventDestroy(e);
   if (staged_) (void)hipEventDestroy(staged_);
   if (reset_staged_) {
@@ -248,12 +283,13 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipEventCreateWithFlags(&staged_, hipEventDisableTiming));
   RDX_HIP(hipEventCreate(&tune_ev_[0]));
   RDX_HIP(hipEventCreate(&tune_ev_[1]));
-  RDX_HIP(hipMemcpy(model_, &model_host_, sizeof model_host_, hipMemcpyHostToDevice));
-  RDX_HIP(hipMemset(d_n_tiles_, 0, sizeof(int32_t)));
-  RDX_HIP(hipMemset(d_base_, 0, sizeof(int32_t)));
-  RDX_HIP(hipMemset(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_));
-  RDX_HIP(hipMemset(evq_count_, 0, sizeof(unsigned long long) * 2 * kBins * kQueues * kQueueStride));
-  RDX_HIP(hipDeviceSynchronize());
+  RDX_HIP(hipStreamCreateWithFlags(&own_, hipStreamNonBlocking));
+  RDX_HIP(hipMemcpyAsync(model_, &model_host_, sizeof model_host_, hipMemcpyHostToDevice, own_));
+  RDX_HIP(hipMemsetAsync(d_n_tiles_, 0, sizeof(int32_t), own_));
+  RDX_HIP(hipMemsetAsync(d_base_, 0, sizeof(int32_t), own_));
+  RDX_HIP(hipMemsetAsync(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_, own_));
+  RDX_HIP(hipMemsetAsync(evq_count_, 0, sizeof(unsigned long long) * 2 * kBins * kQueues * kQueueStride, own_));
+  RDX_HIP(hipStreamSynchronize(own_));
   return RDX_OK;
 }
 
@@ -266,6 +302,7 @@ bool Engine::compatible(const HostInstance& I) const {
 }
 
 rdx_status Engine::add_run(Run* r, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   const HostInstance& I = r->host;
   if (!compatible(I)) return set_error(RDX_EINVAL, "run does not share the engine's species/reaction structure");
   if (resident_runs_ >= max_runs_ || resident_tets_ + I.T > max_tets_)
@@ -337,6 +374,7 @@ void Engine::remove_run(Run* r, hipStream_t stream) {
 }
 
 rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   const size_t n = (size_t)r->host.S * (size_t)r->host.T;
   RDX_HIP(hipMemsetAsync(r->cnt[(r->window + 1) & 1], 0, sizeof(int32_t) * n, stream));
   RDX_HIP(hipMemsetAsync(r->tally, 0, sizeof(unsigned long long) * kTallyWords * kTallySlots, stream));
@@ -345,6 +383,7 @@ rdx_status Engine::reset_run(Run* r, hipStream_t stream) {
 }
 
 rdx_status Engine::reset_runs_device(Run* const* runs, size_t n, const int32_t* const* src, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   size_t n_chunks = 0;
   for (size_t j = 0; j < n; ++j) {
     const int64_t e = (int64_t)runs[j]->host.S * runs[j]->host.T;
@@ -389,6 +428,7 @@ rdx_status Engine::reset_runs_device(Run* const* runs, size_t n, const int32_t* 
 }
 
 rdx_status Engine::upload_counts(Run* r, const int32_t* counts, bool device, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   const size_t n = (size_t)r->host.S * (size_t)r->host.T;
   RDX_HIP(hipMemcpyAsync(r->cnt[r->window & 1], counts, sizeof(int32_t) * n,
                          device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream));
@@ -397,6 +437,7 @@ rdx_status Engine::upload_counts(Run* r, const int32_t* counts, bool device, hip
 }
 
 rdx_status Engine::set_rates(Run* r, const double* kcst, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   const size_t n = (size_t)r->host.n_regions * (size_t)r->host.R;
   for (size_t i = 0; i < n; ++i)
     if (!(kcst[i] >= 0.0) || !std::isfinite(kcst[i]))
@@ -417,13 +458,15 @@ rdx_status Engine::set_rates(Run* r, const double* kcst, hipStream_t stream) {
 }
 
 rdx_status Engine::region_counts(const Run* r, unsigned long long* scratch, unsigned long long* out,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, bool mark) {
   RDX_HIP(launch_region_counts(r->cnt[r->window & 1], r->region, r->host.T, r->host.S, r->host.n_regions,
                                scratch, out, stream));
+  if (mark) fence(stream);
   return RDX_OK;
 }
 
 rdx_status Engine::download_counts(const Run* r, int32_t* out, bool device, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   const size_t n = (size_t)r->host.S * (size_t)r->host.T;
   RDX_HIP(hipMemcpyAsync(out, r->cnt[r->window & 1], sizeof(int32_t) * n,
                          device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, stream));
@@ -667,6 +710,7 @@ void Engine::set_autotune(bool on) {
 }
 
 rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
+  FenceOnExit fence_on_exit{this, stream};
   std::vector<Run*> active;
   int64_t K = 0;
   for (Run* r : runs)
@@ -814,16 +858,35 @@ rdx_status Engine::kernel_times(rdx_kernel_times* out, bool reset) {
 }
 
 rdx_status Engine::run_error(const Run* r) const {
+  // on the engine's own stream: a copy on the legacy default stream is refused
+  // while any other thread holds a blocking stream in graph capture
   int32_t flags = 0;
-  RDX_HIP(hipMemcpy(&flags, r->err, sizeof flags, hipMemcpyDeviceToHost));
+  RDX_HIP(hipMemcpyAsync(&flags, r->err, sizeof flags, hipMemcpyDeviceToHost, own_));
+  RDX_HIP(hipStreamSynchronize(own_));
   if (flags & kErrOverflow) return set_error(RDX_EOVERFLOW, "a molecule count passed 2^30");
   if (flags & kErrEvents) return set_error(RDX_EEVENTS, "more than 2^22 SSA events in one tet window");
   return RDX_OK;
 }
 
+rdx_status Engine::read_run_async(const Run* r, Readout* out, hipStream_t stream) const {
+  RDX_HIP(hipMemcpyAsync(&out->err, r->err, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  RDX_HIP(hipMemcpyAsync(out->slots, r->tally, sizeof out->slots, hipMemcpyDeviceToHost, stream));
+  return RDX_OK;
+}
+
+rdx_status Engine::decode_readout(const Readout& in, unsigned long long tal[3]) {
+  tal[0] = tal[1] = tal[2] = 0;
+  for (int j = 0; j < kTallySlots; ++j)
+    for (int q = 0; q < 3; ++q) tal[q] += in.slots[kTallyWords * j + q];
+  if (in.err & kErrOverflow) return set_error(RDX_EOVERFLOW, "a molecule count passed 2^30");
+  if (in.err & kErrEvents) return set_error(RDX_EEVENTS, "more than 2^22 SSA events in one tet window");
+  return RDX_OK;
+}
+
 rdx_status Engine::run_tally(const Run* r, unsigned long long tal[3]) const {
   unsigned long long slots[kTallyWords * kTallySlots];
-  RDX_HIP(hipMemcpy(slots, r->tally, sizeof slots, hipMemcpyDeviceToHost));
+  RDX_HIP(hipMemcpyAsync(slots, r->tally, sizeof slots, hipMemcpyDeviceToHost, own_));
+  RDX_HIP(hipStreamSynchronize(own_));
   tal[0] = tal[1] = tal[2] = 0;
   for (int j = 0; j < kTallySlots; ++j)
     for (int q = 0; q < 3; ++q) tal[q] += slots[kTallyWords * j + q];

@@ -131,8 +131,10 @@ class Engine {
   rdx_status set_rates(Run* r, const double* kcst, hipStream_t stream);
   // Recording: per-region sums of the current counts into the device array
   // out [n_regions*S], enqueued on `stream`; scratch holds kRegionScratchBytes.
+  // `mark` = false leaves `stream` out of the fences (no event is recorded,
+  // for callers under graph capture).
   rdx_status region_counts(const Run* r, unsigned long long* scratch, unsigned long long* out,
-                           hipStream_t stream);
+                           hipStream_t stream, bool mark = true);
   // Recording inside a sequence: while set, sequence() launches plain
   // windows (no tuning, no graphs) and after every `every`-th window of
   // `run` writes its per-region sums to ring slot (records mod slots).
@@ -169,9 +171,31 @@ class Engine {
   void set_timing(bool on) { timing_ = on; }
   rdx_status kernel_times(rdx_kernel_times* out, bool reset);
 
-  rdx_status run_error(const Run* r) const;  // device error flag of one run (synchronous)
+  // Device error flag of one run, and its tallies; synchronous, on the
+  // engine's own stream, so the caller first waits for the stream that ran
+  // the run's windows.
+  rdx_status run_error(const Run* r) const;
   // SSA events, molecules moved, nonzero (tet, species, face) moves
   rdx_status run_tally(const Run* r, unsigned long long tal[3]) const;
+  // The same two read back on `stream` into `out` (pinned host memory), so
+  // that only that stream is waited for; `out` is valid once it has been
+  // synchronised, and decode_readout then gives the error and the tallies.
+  struct Readout {
+    int32_t err;
+    int32_t pad;
+    unsigned long long slots[kTallyWords * kTallySlots];
+  };
+  rdx_status read_run_async(const Run* r, Readout* out, hipStream_t stream) const;
+  static rdx_status decode_readout(const Readout& in, unsigned long long tal[3]);
+
+  // The engine's own stream, for set-up work that has no caller stream.
+  hipStream_t own_stream() const { return own_; }
+  // Every method that enqueues on a stream marks it here; drain() waits for
+  // the last enqueue on each marked stream.  The engine's memory can then be
+  // released without a device-wide synchronisation, which fails while any
+  // other thread holds a stream in graph capture.
+  void fence(hipStream_t stream);
+  void drain();
 
   int S() const { return S_; }
   int R() const { return R_; }
@@ -226,6 +250,8 @@ class Engine {
 
   // graphs by (windows, grids); captured on a private stream
   hipStream_t capture_stream_ = nullptr;
+  hipStream_t own_ = nullptr;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> fences_;
   RecordHook rec_{};
   bool rec_on_ = false;
   std::map<std::pair<int, long long>, hipGraphExec_t> graphs_;

@@ -2,12 +2,12 @@
 //
 // Requests (a mesh, model parameters, seed, initial counts and t_end) are set
 // up on the submitting thread (validation and the set-up step of section 2.1)
-// and queued.  One worker thread owns the device side: between scheduling
-// ticks it admits queued requests in arrival order while the device budget
-// has room for their state, then runs one tick -- up to `tick_windows`
-// windows of every resident request, all in the same window launches -- and
-// retires the requests that reached their t_end, which frees their memory for
-// the next admissions.  Requests therefore join and leave a running batch;
+// and queued.  One worker thread owns the device side: it admits queued
+// requests in arrival order while the device budget has room for their
+// state, enqueues one tick -- up to `tick_windows` windows of every resident
+// request, all in the same window launches -- and retires the requests that
+// reached their t_end, which frees their memory for the next admissions.
+// Requests therefore join and leave a running batch;
 // each one's result is the one it would get alone, since every draw is
 // addressed by (its seed, stream, tet, its window index).
 #include <hip/hip_runtime_api.h>
@@ -61,7 +61,10 @@ double quantile(std::vector<double> v, double q) {
 struct rdx_server {
   Engine eng;
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;     // the ticks' launches
+  hipStream_t up_stream = nullptr;  // admissions' uploads, retirements' reads
+  hipEvent_t tick_begin[2] = {nullptr, nullptr}, tick_end[2] = {nullptr, nullptr};
+  Engine::Readout* readout = nullptr;  // pinned, one per resident run
   int tick_windows = 8;
   int64_t capacity_tets = 0;
   std::chrono::steady_clock::time_point t0;
@@ -77,7 +80,8 @@ struct rdx_server {
   // statistics (under mu)
   int64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, ticks = 0;
   int64_t voxel_steps = 0, ssa_events = 0, moves = 0;
-  double busy_s = 0.0;
+  double gpu_busy_s = 0.0;  // device time of the retired ticks (HIP events)
+  double host_s = 0.0;      // worker time spent on uploads, planning and launching
   std::vector<double> latencies;
 
   std::thread worker;
@@ -85,7 +89,19 @@ struct rdx_server {
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  ~rdx_server() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    if (up_stream) (void)hipStreamSynchronize(up_stream);
+    for (int j = 0; j < 2; ++j) {
+      if (tick_begin[j]) (void)hipEventDestroy(tick_begin[j]);
+      if (tick_end[j]) (void)hipEventDestroy(tick_end[j]);
+    }
+    if (readout) (void)hipHostFree(readout);
+    if (up_stream) (void)hipStreamDestroy(up_stream);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
   void run_loop();
+  void retire(std::vector<Request*>& leaving, int slot, rdx_status tick_st, const std::string& tick_err);
   void finish(Request* q, int32_t state, rdx_status st, const std::string& msg);
 };
 
@@ -109,13 +125,71 @@ void rdx_server::finish(Request* q, int32_t state, rdx_status st, const std::str
   cv_done.notify_all();
 }
 
+void rdx_server::retire(std::vector<Request*>& leaving, int slot, rdx_status tick_st, const std::string& tick_err) {
+  // every launch that can touch these runs is in tick `slot`, already enqueued
+  // on `stream`: the reads go on the side stream behind that tick's end event,
+  // so the tick enqueued after it keeps the device busy meanwhile.  With no
+  // leavers the worker still waits for the tick's end, so that at most two
+  // ticks are ever enqueued.
+  if (leaving.empty()) {
+    (void)hipEventSynchronize(tick_end[slot]);
+    return;
+  }
+  if (hipStreamWaitEvent(up_stream, tick_end[slot], 0) != hipSuccess) {
+    tick_st = RDX_EHIP;
+    (void)hipStreamSynchronize(stream);
+  }
+  for (size_t j = 0; j < leaving.size(); ++j) {
+    Request* q = leaving[j];
+    const bool done = q->run.t >= q->t_end;
+    rdx_status rs = tick_st;
+    std::string msg = tick_err;
+    if (rs == RDX_OK && done) {  // a finished request is delivered even if cancelled late
+      Engine::Readout* ro = readout + j;
+      rs = eng.read_run_async(&q->run, ro, up_stream);
+      if (rs == RDX_OK) rs = eng.download_counts(&q->run, q->counts0.data(), false, up_stream);
+      unsigned long long tal[3] = {0, 0, 0};
+      if (rs == RDX_OK) {
+        rs = Engine::decode_readout(*ro, tal);
+        if (rs != RDX_OK) msg = rdx_last_error();
+      } else {
+        msg = rdx_last_error();
+      }
+      q->stats.windows = q->run.windows_run;
+      q->stats.voxel_steps = q->run.voxel_steps;
+      q->stats.ssa_events = (int64_t)tal[0];
+      q->stats.moves = (int64_t)tal[1];
+      q->stats.face_moves = (int64_t)tal[2];
+      q->stats.t = q->run.t;
+      q->stats.window_index = q->run.window;
+    }
+    // the side stream has passed the tick's end (and the reads): no launch
+    // can still touch the run
+    eng.remove_run(&q->run, up_stream);
+    std::lock_guard<std::mutex> lk(mu);
+    if (rs == RDX_OK && done) finish(q, RDX_REQ_DONE, RDX_OK, "");
+    else if (rs == RDX_OK) finish(q, RDX_REQ_CANCELLED, RDX_ECANCELLED, "cancelled");
+    else finish(q, RDX_REQ_FAILED, rs, msg);
+  }
+  leaving.clear();
+}
+
 void rdx_server::run_loop() {
   (void)hipSetDevice(device);
+  // Two ticks are in the pipeline at once: while tick n runs on `stream`, the
+  // worker uploads the next admissions on the side stream, enqueues tick n+1
+  // behind tick n, and only then waits for tick n's end event to retire the
+  // requests whose last windows were in it.  Requests leave the resident set
+  // when their last windows are planned, so the tick after never names them.
+  std::vector<Request*> leaving[2];  // per tick slot: retire once it has ended
+  bool in_flight[2] = {false, false};
+  int cur = 0;
   for (;;) {
+    const int prev = cur ^ 1;
     std::vector<Request*> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
-      // queued cancellations end here; resident ones at the tick boundary below
+      // queued cancellations end here; resident ones when their tick is planned
       for (auto it = queue.begin(); it != queue.end();) {
         if ((*it)->cancel || stop) {
           finish(*it, RDX_REQ_CANCELLED, RDX_ECANCELLED, "cancelled");
@@ -139,26 +213,29 @@ void rdx_server::run_loop() {
         queue.pop_front();
         admit.push_back(q);
       }
-      if (stop && resident.empty() && admit.empty()) break;
-      if (resident.empty() && admit.empty()) {
+      const bool idle = resident.empty() && admit.empty() && !in_flight[prev];
+      if (stop && idle) break;
+      if (idle) {
         cv_work.wait(lk, [&] { return stop || !queue.empty(); });
         continue;
       }
     }
-    // uploads of the admitted requests (the device is idle between ticks)
+    // uploads of the admitted requests on the side stream, beside the tick in
+    // flight (add_run and upload_counts wait for the side stream only)
+    const double t_host0 = now();
     for (size_t j = 0; j < admit.size(); ++j) {
       Request* q = admit[j];
-      rdx_status st = eng.add_run(&q->run, stream);
+      rdx_status st = eng.add_run(&q->run, up_stream);
       if (st == RDX_EBUDGET) {  // fragmentation: back to the head of the queue
         std::lock_guard<std::mutex> lk(mu);
         for (size_t x = admit.size(); x-- > j;) queue.push_front(admit[x]);
         break;
       }
-      if (st == RDX_OK) st = eng.reset_run(&q->run, stream);
-      if (st == RDX_OK) st = eng.upload_counts(&q->run, q->counts0.data(), false, stream);
+      if (st == RDX_OK) st = eng.reset_run(&q->run, up_stream);
+      if (st == RDX_OK) st = eng.upload_counts(&q->run, q->counts0.data(), false, up_stream);
       std::lock_guard<std::mutex> lk(mu);
       if (st != RDX_OK) {
-        eng.remove_run(&q->run, stream);
+        eng.remove_run(&q->run, up_stream);
         finish(q, RDX_REQ_FAILED, st, rdx_last_error());
         continue;
       }
@@ -166,56 +243,80 @@ void rdx_server::run_loop() {
       q->t_admit = now();
       resident.push_back(q);
     }
-    // one tick: up to tick_windows windows of every resident request
-    const double tick_start = now();
+    // plan and enqueue the next tick: up to tick_windows windows of every
+    // resident request; cancelled ones leave without windows
     std::vector<Run*> runs;
+    std::vector<Request*> planned, keep;
     bool ok = true;
-    for (Request* q : resident) {
-      if (Engine::plan_until(&q->run, q->t_end, tick_windows) != RDX_OK) ok = false;
-      runs.push_back(&q->run);
-    }
-    rdx_status st = ok ? eng.sequence(runs, stream) : RDX_EINVAL;
-    if (st == RDX_OK && hipStreamSynchronize(stream) != hipSuccess) st = RDX_EHIP;
-    const std::string tick_err = st == RDX_OK ? std::string() : std::string(rdx_last_error());
-    // retire what reached t_end (or failed, or was cancelled)
-    std::vector<Request*> keep;
     for (Request* q : resident) {
       bool cancel;
       {
         std::lock_guard<std::mutex> lk(mu);
         cancel = q->cancel || stop;
       }
-      const bool done = q->run.t >= q->t_end;
-      if (st == RDX_OK && !done && !cancel) {
-        keep.push_back(q);
+      if (cancel) {
+        leaving[prev].push_back(q);  // its last launches are in the tick in flight
         continue;
       }
-      rdx_status rs = st;
-      std::string msg = tick_err;
-      if (rs == RDX_OK && done) {  // a finished request is delivered even if cancelled late
-        rs = eng.run_error(&q->run);
-        if (rs != RDX_OK) msg = rdx_last_error();
-        unsigned long long tal[3] = {0, 0, 0};
-        if (rs == RDX_OK) rs = eng.run_tally(&q->run, tal);
-        if (rs == RDX_OK) rs = eng.download_counts(&q->run, q->counts0.data(), false, stream);
-        q->stats.windows = q->run.windows_run;
-        q->stats.voxel_steps = q->run.voxel_steps;
-        q->stats.ssa_events = (int64_t)tal[0];
-        q->stats.moves = (int64_t)tal[1];
-        q->stats.face_moves = (int64_t)tal[2];
-        q->stats.t = q->run.t;
-        q->stats.window_index = q->run.window;
+      if (Engine::plan_until(&q->run, q->t_end, tick_windows) != RDX_OK) ok = false;
+      runs.push_back(&q->run);
+      planned.push_back(q);
+    }
+    rdx_status st = RDX_OK;
+    if (!planned.empty()) {
+      st = hipEventRecord(tick_begin[cur], stream) == hipSuccess ? RDX_OK : RDX_EHIP;
+      if (st == RDX_OK) st = ok ? eng.sequence(runs, stream) : RDX_EINVAL;
+      if (st == RDX_OK && hipEventRecord(tick_end[cur], stream) != hipSuccess) st = RDX_EHIP;
+    }
+    const std::string tick_err = st == RDX_OK ? std::string() : std::string(rdx_last_error());
+    if (st != RDX_OK) {
+      // a failed tick may have enqueued part of its launches: retire its
+      // requests once the stream has drained
+      (void)hipStreamSynchronize(stream);
+      for (Request* q : planned) {
+        eng.remove_run(&q->run, stream);
+        std::lock_guard<std::mutex> lk(mu);
+        finish(q, RDX_REQ_FAILED, st, tick_err);
       }
-      eng.remove_run(&q->run, stream);
-      std::lock_guard<std::mutex> lk(mu);
-      if (rs == RDX_OK && done) finish(q, RDX_REQ_DONE, RDX_OK, "");
-      else if (rs == RDX_OK) finish(q, RDX_REQ_CANCELLED, RDX_ECANCELLED, "cancelled");
-      else finish(q, RDX_REQ_FAILED, rs, msg);
+      planned.clear();
+    }
+    for (Request* q : planned) {
+      if (q->run.t >= q->t_end) leaving[cur].push_back(q);
+      else keep.push_back(q);
     }
     resident.swap(keep);
-    std::lock_guard<std::mutex> lk(mu);
-    ticks += 1;
-    busy_s += now() - tick_start;
+    const bool launched = !planned.empty();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      host_s += now() - t_host0;
+    }
+    // retire the previous tick's leavers (this waits for its end only)
+    if (in_flight[prev] || !leaving[prev].empty()) {
+      if (in_flight[prev]) {
+        retire(leaving[prev], prev, RDX_OK, std::string());
+        float ms = 0.f;
+        if (hipEventSynchronize(tick_end[prev]) == hipSuccess &&
+            hipEventElapsedTime(&ms, tick_begin[prev], tick_end[prev]) == hipSuccess) {
+          std::lock_guard<std::mutex> lk(mu);
+          gpu_busy_s += 1e-3 * (double)ms;
+        }
+      } else {  // cancelled while nothing was in flight
+        (void)hipStreamSynchronize(stream);
+        for (Request* q : leaving[prev]) {
+          eng.remove_run(&q->run, stream);
+          std::lock_guard<std::mutex> lk(mu);
+          finish(q, RDX_REQ_CANCELLED, RDX_ECANCELLED, "cancelled");
+        }
+        leaving[prev].clear();
+      }
+      in_flight[prev] = false;
+    }
+    in_flight[cur] = launched;  // leaving[cur] is empty unless it launched
+    if (launched) {
+      std::lock_guard<std::mutex> lk(mu);
+      ticks += 1;
+    }
+    cur ^= 1;
   }
 }
 
@@ -262,8 +363,15 @@ rdx_status rdx_server_create(const rdx_model* structure, const rdx_server_option
   if (st != RDX_OK) return st;
   const int gw = opts->graph_windows ? opts->graph_windows : s->tick_windows;
   s->eng.set_shape(ExecShape{1, gw, 4});
-  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+  if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) != hipSuccess)
     return set_error(RDX_EHIP, "stream creation failed");
+  for (int j = 0; j < 2; ++j)
+    if (hipEventCreate(&s->tick_begin[j]) != hipSuccess || hipEventCreate(&s->tick_end[j]) != hipSuccess)
+      return set_error(RDX_EHIP, "event creation failed");
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->readout), sizeof(Engine::Readout) * (size_t)max_runs) !=
+      hipSuccess)
+    return set_error(RDX_ENOMEM, "pinned host allocation failed");
   s->t0 = std::chrono::steady_clock::now();
   rdx_server* raw = s.get();
   s->worker = std::thread([raw] { raw->run_loop(); });
@@ -280,8 +388,6 @@ void rdx_server_destroy(rdx_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   (void)hipSetDevice(s->device);
-  (void)hipStreamSynchronize(s->stream);
-  (void)hipStreamDestroy(s->stream);
   delete s;
 }
 
@@ -403,7 +509,8 @@ rdx_status rdx_server_get_stats(rdx_server* s, rdx_server_stats* out) {
   out->voxel_steps = s->voxel_steps;
   out->ssa_events = s->ssa_events;
   out->moves = s->moves;
-  out->busy_s = s->busy_s;
+  out->busy_s = s->gpu_busy_s;
+  out->worker_s = s->host_s;
   out->uptime_s = s->now();
   out->latency_p50_s = quantile(s->latencies, 0.50);
   out->latency_p99_s = quantile(s->latencies, 0.99);

@@ -152,7 +152,7 @@ class _ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "cancelled", "queued",
                                          "running", "ticks", "voxel_steps", "ssa_events", "moves")] + \
                [(n, C.c_double) for n in ("busy_s", "uptime_s", "latency_p50_s", "latency_p99_s")] + \
-               [("capacity_tets", C.c_int64)]
+               [("capacity_tets", C.c_int64), ("worker_s", C.c_double)]
 
 
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}

@@ -76,6 +76,33 @@ def test_results_equal_alone_and_in_the_mix(rdx, oracle_lib):
         np.testing.assert_array_equal(results[j][0], ref.counts)
         assert results[j][1]["stats"].ssa_events == ref.tallies.ssa_events
     assert st["latency_p50_s"] > 0 and st["latency_p99_s"] >= st["latency_p50_s"]
+    # device time of the ticks and the worker's own time are both inside the uptime
+    assert 0 < st["busy_s"] <= st["uptime_s"] and 0 < st["worker_s"] <= st["uptime_s"]
+    assert st["ticks"] > 0
+    srv.close()
+
+
+def test_zero_length_and_back_to_back_requests(rdx):
+    """A request with t_end = 0 returns its initial counts after no window;
+    requests submitted while ticks are in flight, finishing on successive
+    ticks, each equal the same simulation alone."""
+    reqs = _requests(6, seed=13, t_lo=300, t_hi=600)
+    model = reqs[0][1].model.as_dict()
+    srv = rdx.Server(model, hbm_budget_bytes=64 << 20, tick_windows=3)
+    w0 = reqs[0][1]
+    tk0 = srv.submit(w0.mesh.as_dict(), model, w0.seed, w0.counts, 0.0)
+    tks = []
+    for j, (_, w) in enumerate(reqs[1:]):
+        w.t_end = w.t_end * (1 + 0.37 * j)  # ends spread over several ticks
+        tks.append(srv.submit(w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts, w.t_end))
+    c0, info0 = srv.wait(tk0, timeout_s=60.0)
+    np.testing.assert_array_equal(c0, w0.counts)
+    assert info0["stats"].windows == 0 and info0["state"] == "done"
+    for tk, (_, w) in zip(tks, reqs[1:]):
+        c, info = srv.wait(tk, timeout_s=60.0)
+        ref_c, ref_st = _solo(rdx, w)
+        np.testing.assert_array_equal(c, ref_c)
+        assert info["stats"] == ref_st
     srv.close()
 
 
