@@ -1009,19 +1009,27 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
         for (int s = 0; s < SMAX; ++s)
           if (((dmask >> s) & 1u) && n_own[s] > 0) mask |= 1u << s;
       }
-      // items with more than 16 molecules (a binomial count each) first, so
-      // that few rounds wait on a binomial; then the rest; species-major
-      // within each class
+      // items in three classes, each species-major: more than 16 molecules
+      // (a binomial count each), so that few rounds wait on a binomial; then
+      // 5 to 16 (two to four Philox calls on the item's lane); then 1 to 4
+      // (one call).  A round's lanes step through as many calls as its
+      // longest item has, so grouping items by their number of calls keeps
+      // the short ones from idling behind the long ones.
       int total = 0, errbits = 0;
       const unsigned long long below = (1ull << lane) - 1ull;
-      uint32_t large = 0;  // species of this tet with more than 16 molecules
+      uint32_t large = 0, multi = 0;  // species of this tet in the first two classes
 #pragma unroll
       for (int s = 0; s < SMAX; ++s)
-        if (((mask >> s) & 1u) && n_own[s] > kSmallM) large |= 1u << s;
-      const int n_cls = __ballot(large != 0u) ? 2 : 1;  // uniform
+        if ((mask >> s) & 1u) {
+          if (n_own[s] > kSmallM) large |= 1u << s;
+          else if (n_own[s] > 4) multi |= 1u << s;
+        }
+      const bool any_large = __ballot(large != 0u) != 0ull;  // uniform
+      const bool any_multi = __ballot(multi != 0u) != 0ull;
 #pragma unroll 1
-      for (int cls = 0; cls < n_cls; ++cls) {
-        const uint32_t cm = n_cls == 1 ? mask : (cls == 0 ? large : mask & ~large);
+      for (int cls = 0; cls < 3; ++cls) {
+        if ((cls == 0 && !any_large) || (cls == 1 && !any_multi)) continue;
+        const uint32_t cm = cls == 0 ? large : (cls == 1 ? multi : mask & ~(large | multi));
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) {
           const bool has = (cm >> s) & 1u;
@@ -1055,8 +1063,18 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
           Ln = (int)((itw >> 4) & 63);
           sp = (int)(itw & 15);
           m = (int)(itw >> 10);
-          if (m == 0) m = cc.cin[(size_t)sp * T + base + Ln];  // an unpacked large count
           tnb = L.nbr[Ln];
+        }
+        // A count of 2^22 or more does not fit the packed field (0 marks
+        // it): its lane reads it from the count buffer, in a rare uniform
+        // branch that hands the value on through LDS.  Any later use of a
+        // register still awaiting a global load would otherwise make the
+        // whole round wait on the vector-memory counter, i.e. for the next
+        // tile's loads and this tile's atomics as well.
+        if (__ballot(in.valid && m == 0) != 0ull) {
+          if (in.valid && m == 0) L.item[r0 + lane] = (uint32_t)cc.cin[(size_t)sp * T + base + Ln];
+          wave_sync();
+          if (in.valid && m == 0) m = (int)L.item[r0 + lane];
         }
         in.sp = sp;
         in.ln = Ln;
