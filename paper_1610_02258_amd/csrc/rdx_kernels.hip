@@ -668,6 +668,47 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
   return r;
 }
 
+// item_round for a round in which every item is a diffusion-only tet's
+// species with at most 16 molecules (mean occupancy = count = npost, so no
+// rounding draw, no binomial, no cap, words 0 .. m-1 of the stream): the
+// same draws and decisions as item_round's own-lane path, without its
+// set-up for the other cases.
+__device__ __forceinline__ ItemMoves item_round_small(uint32_t key0, uint32_t key1, uint32_t window,
+                                                     const ItemIn& it, const ItemView& V) {
+  uint32_t own = 0;  // leavers by face, a byte each
+  if (it.valid) {
+    const uint32_t tet = V.tet_of(it.ln);
+    const double p = item_p(V, it.sp, it.ln);
+    const uint32_t m = (uint32_t)it.npost;
+    if (p > 0.0) {
+      const int last = last_face(V.nbr[it.ln]);
+      const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
+      const double t0 = p * g0.y, t1 = p * g1.x, t2 = p * g1.y;
+      const uint32_t calls = (m + 3u) >> 2;
+      for (uint32_t call = 0; call < calls; ++call) {
+        uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
+        philox4x32_10(x0, x1, x2, x3, key0, key1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
+          const double u = (double)w * 0x1p-32;
+          if (4u * call + (uint32_t)q < m && u < p) {
+            const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
+            own += 1u << (8 * f);
+          }
+        }
+      }
+    }
+  }
+  ItemMoves r;
+  r.o0 = (int)(own & 0xffu);
+  r.o1 = (int)((own >> 8) & 0xffu);
+  r.o2 = (int)((own >> 16) & 0xffu);
+  r.o3 = (int)(own >> 24);
+  r.n = r.o0 + r.o1 + r.o2 + r.o3;
+  return r;
+}
+
 // Tile schedule of a persistent block: the blocks are dispatched round-robin
 // over the 8 XCDs, so XCD x (= block % 8) owns one contiguous range of tiles
 // (its L2 then sees neighbouring tets), shared round-robin by its blocks.
@@ -1080,7 +1121,9 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
         in.ln = Ln;
         in.nbar = (double)m;
         in.npost = m;
-        const ItemMoves mv = item_round(key0, key1, cc.window, in, view, L.x);
+        const bool big_round = __ballot(in.valid && m > kSmallM) != 0ull;  // uniform
+        const ItemMoves mv = big_round ? item_round(key0, key1, cc.window, in, view, L.x)
+                                       : item_round_small(key0, key1, cc.window, in, view);
         if (in.valid) {
           // own remainder and moves to the tile's own tets go to LDS, the
           // rest to the next count buffer
