@@ -201,10 +201,13 @@ def roofline(T: int, S: int, n_regions: int, windows: int, face_moves: int, kt: 
 
 
 def _apply_shape(sim, shape: str):
-    """Online tuning of the launch shape, or the fixed shape 'div,graph,group'."""
+    """Online tuning of the launch shape, or the fixed shape
+    'div,graph,group[,claim]' (claim: diffusion tiles claimed at run time)."""
     if shape:
-        d, g, e = (int(x) for x in shape.split(","))
-        sim.set_exec_options(autotune=False, fast_grid_div=d, graph_windows=g, event_group=e)
+        v = [int(x) for x in shape.split(",")]
+        d, g, e = v[:3]
+        c = v[3] if len(v) > 3 else 0
+        sim.set_exec_options(autotune=False, fast_grid_div=d, graph_windows=g, event_group=e, tile_claim=c)
     else:
         sim.set_exec_options(autotune=True)
 
@@ -393,7 +396,7 @@ def batched_leg(steps: int = 2) -> dict:
 
     # warm-up, which also runs the online tuning of the launch shape (its
     # candidate shapes are timed on real windows; a step may not hold them all)
-    for _ in range(6):
+    for _ in range(12):
         batch_step()
         torch.cuda.synchronize()
         if not b.exec_options()["autotune"]:
@@ -725,7 +728,7 @@ def main() -> int:
     ap.add_argument("--simple", action="store_true",
                     help="instead of the headline line, print the simple-model leg (steps = its steps)")
     ap.add_argument("--shape", default="",
-                    help="fixed launch shape 'grid_div,graph_windows,event_group' for the headline and the "
+                    help="fixed launch shape 'grid_div,graph_windows,event_group[,tile_claim]' for the headline and the "
                          "simple leg instead of online tuning (for reproducible profiles)")
     ap.add_argument("--no-extra", action="store_true",
                     help="leave the density/refinement series and the forcing leg out of the line")

@@ -261,13 +261,19 @@ rdx_status rdx_load(rdx_sim* sim, const void* buf, size_t len, void* stream);
  *                  packed into event chunks of their own, so that a chunk's
  *                  lanes, which run their SSA chains in lock-step, have
  *                  chains of similar length (load balancing of skewed event
- *                  loads, section 3.2); 0: one queue.  Default 1. */
+ *                  loads, section 3.2); 0: one queue.  Default 1.
+ *   tile_claim     1: after its first tile, a diffusion block claims its
+ *                  next tile at run time from a counter of its XCD's tile
+ *                  range, so that blocks finish within about one tile of each
+ *                  other where tiles differ in cost (molecules clustered in
+ *                  part of the mesh); 0: static tile ranges.  Default 0. */
 typedef struct rdx_exec_options {
   int32_t autotune;
   int32_t fast_grid_div;
   int32_t graph_windows;
   int32_t event_group;
   int32_t event_bins;
+  int32_t tile_claim;
 } rdx_exec_options;
 
 rdx_status rdx_set_exec_options(rdx_sim* sim, const rdx_exec_options* opts);
@@ -414,7 +420,7 @@ const char* rdx_last_error(void);
 
 /* ABI version of this header (major * 100 + minor); the library returns
  * RDX_ABI_VERSION of the header it was built from. */
-#define RDX_ABI_VERSION 208
+#define RDX_ABI_VERSION 209
 int32_t rdx_version(void);
 
 /* ---- device self-tests of the random layer (host pointers, synchronous) ---- */

@@ -131,7 +131,9 @@ rdx_status apply_options(Engine& eng, const rdx_exec_options* o) {
     return set_error(RDX_EINVAL,
                      "fast_grid_div must be 1, 2 or 4, graph_windows in [1, 256], event_group in [0, 64]");
   if (o->event_bins < 0 || o->event_bins > 1) return set_error(RDX_EINVAL, "event_bins must be 0 or 1");
-  eng.set_shape(ExecShape{o->fast_grid_div, o->graph_windows, o->event_group ? o->event_group : 4, o->event_bins});
+  if (o->tile_claim < 0 || o->tile_claim > 1) return set_error(RDX_EINVAL, "tile_claim must be 0 or 1");
+  eng.set_shape(ExecShape{o->fast_grid_div, o->graph_windows, o->event_group ? o->event_group : 4, o->event_bins,
+                          o->tile_claim});
   if (o->autotune) eng.set_autotune(true);
   return RDX_OK;
 }
@@ -142,6 +144,7 @@ void read_options(const Engine& eng, rdx_exec_options* o) {
   o->graph_windows = eng.shape().graph_windows;
   o->event_group = eng.shape().event_group;
   o->event_bins = eng.shape().event_bins;
+  o->tile_claim = eng.shape().tile_claim;
 }
 
 }  // namespace

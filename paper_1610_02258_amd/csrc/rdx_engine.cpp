@@ -243,6 +243,7 @@ Engine::~Engine() {
   (void)hipFree(evq_);
   (void)hipFree(evq_count_);
   (void)hipFree(wl_tet_);
+  (void)hipFree(tile_ctr_);
   if (h_runs_) (void)hipHostFree(h_runs_);
   if (h_tile_map_) (void)hipHostFree(h_tile_map_);
   if (h_n_tiles_) (void)hipHostFree(h_n_tiles_);
@@ -271,7 +272,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
             dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&evq_, (size_t)kBins * kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
             dev_alloc(&evq_count_, (size_t)2 * kBins * kQueues * kQueueStride) == hipSuccess &&
-            dev_alloc(&wl_tet_, W) == hipSuccess;
+            dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&tile_ctr_, (size_t)2 * 8 * kCtrStride) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
@@ -289,6 +290,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemsetAsync(d_base_, 0, sizeof(int32_t), own_));
   RDX_HIP(hipMemsetAsync(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_, own_));
   RDX_HIP(hipMemsetAsync(evq_count_, 0, sizeof(unsigned long long) * 2 * kBins * kQueues * kQueueStride, own_));
+  RDX_HIP(hipMemsetAsync(tile_ctr_, 0, sizeof(int32_t) * 2 * 8 * kCtrStride, own_));
   RDX_HIP(hipStreamSynchronize(own_));
   return RDX_OK;
 }
@@ -661,7 +663,8 @@ rdx_status Engine::launch_graphs(const StepArgs& a0, int64_t reps, hipStream_t s
   const int W = shape_.graph_windows;
   // everything of the arguments that can change between sequences is in the
   // key (pointers and tables are fixed for the engine's life)
-  const long long shape_key = ((long long)a0.main_grid << 40) | ((long long)a0.detect_grid << 9) |
+  const long long shape_key = ((long long)a0.main_grid << 40) | ((long long)(a0.tile_claim ? 1 : 0) << 35) |
+                              ((long long)a0.detect_grid << 9) |
                               ((long long)(a0.heavy_events < 1e300 ? 1 : 0) << 8) |
                               ((long long)a0.ev_group_max << 1) | (long long)a0.single_run;
   const auto key = std::make_pair(W, shape_key);
@@ -701,9 +704,10 @@ void Engine::set_autotune(bool on) {
   // then every shape twice, in two passes, each scored by its better pass,
   // so that a drift of the per-window cost over the tuning windows (a
   // simulation relaxing from its initial counts) biases the choice less
-  const ExecShape shapes[] = {ExecShape{1, 1, 4}, ExecShape{2, 1, 4}, ExecShape{1, 8, 4},  ExecShape{2, 8, 4},
-                              ExecShape{4, 8, 4}, ExecShape{1, 8, 8}, ExecShape{1, 8, 16}, ExecShape{1, 8, 64},
-                              ExecShape{1, 1, 64}};
+  const ExecShape shapes[] = {ExecShape{1, 1, 4},        ExecShape{2, 1, 4},       ExecShape{1, 8, 4},
+                              ExecShape{2, 8, 4},        ExecShape{4, 8, 4},       ExecShape{1, 8, 8},
+                              ExecShape{1, 8, 16},       ExecShape{1, 8, 64},      ExecShape{1, 1, 64},
+                              ExecShape{1, 1, 4, 1, 1},  ExecShape{1, 8, 16, 1, 1}};
   candidates_.push_back(shapes[0]);
   for (int pass = 0; pass < 2; ++pass)
     for (const ExecShape& c : shapes) candidates_.push_back(c);
@@ -753,11 +757,13 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
   a.evq_cap = (int32_t)((max_tiles_ + kQueues - 1) / kQueues);
   a.evq_count = evq_count_;
   a.wl_tet = wl_tet_;
+  a.tile_ctr = tile_ctr_;
 
   auto run_chunk = [&](const ExecShape& sh, int64_t n) -> rdx_status {
     grids_for(n_tiles, sh.fast_grid_div, &a.detect_grid, &a.main_grid);
     a.ev_group_max = sh.event_group;
     a.heavy_events = heavy_events(sh);
+    a.tile_claim = sh.tile_claim;
     const ExecShape keep = shape_;
     shape_ = sh;
     rdx_status r = RDX_OK;
@@ -777,6 +783,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
     grids_for(n_tiles, shape_.fast_grid_div, &a.detect_grid, &a.main_grid);
     a.ev_group_max = shape_.event_group;
     a.heavy_events = heavy_events(shape_);
+    a.tile_claim = shape_.tile_claim;
     st = launch_plain(a, K, stream);
     if (st != RDX_OK) return st;
     done = K;
@@ -788,6 +795,7 @@ rdx_status Engine::sequence(const std::vector<Run*>& runs, hipStream_t stream) {
       grids_for(n_tiles, c.fast_grid_div, &a.detect_grid, &a.main_grid);
       a.ev_group_max = c.event_group;
       a.heavy_events = heavy_events(c);
+      a.tile_claim = c.tile_claim;
       const ExecShape keep = shape_;
       shape_ = c;
       st = launch_graphs(a, 0, stream);

@@ -83,11 +83,13 @@ struct ExecShape {
   int graph_windows = 1;
   int event_group = 4;  // most queued tiles packed into one event chunk
   int event_bins = 1;   // listed tets binned by expected events (heavy, light)
+  int tile_claim = 0;   // diffusion tiles after the first claimed at run time
   bool operator<(const ExecShape& o) const {
     if (fast_grid_div != o.fast_grid_div) return fast_grid_div < o.fast_grid_div;
     if (graph_windows != o.graph_windows) return graph_windows < o.graph_windows;
     if (event_group != o.event_group) return event_group < o.event_group;
-    return event_bins < o.event_bins;
+    if (event_bins != o.event_bins) return event_bins < o.event_bins;
+    return tile_claim < o.tile_claim;
   }
 };
 
@@ -231,6 +233,7 @@ class Engine {
   int32_t* evq_ = nullptr;
   unsigned long long* evq_count_ = nullptr;
   int32_t* wl_tet_ = nullptr;
+  int32_t* tile_ctr_ = nullptr;  // [2][8][kCtrStride]
 
   // pinned staging of the run table and tile map; `staged_` marks the
   // completion of the last upload from them

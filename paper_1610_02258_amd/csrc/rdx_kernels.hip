@@ -983,6 +983,17 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   const int S = A.S;
   const int n_tiles = *as_const(A.n_tiles);
   const TileRange tr = tile_range(b, G, n_tiles);
+  // Run-time claiming (a launch-shape setting, for workloads whose tiles
+  // differ in cost): the block's first tile is its static one, lo + j; the
+  // tiles from lo + Gx on are handed out in order by its XCD's counter, each
+  // claim issued one tile ahead so that its latency hides behind a tile's
+  // work.  A block stops at its first claim past the range, so every block
+  // ends, and the slowest finishes within about one tile of the others.
+  const bool claim = A.tile_claim != 0 && G >= 8 && n_tiles >= 8;
+  int32_t* const ctr = A.tile_ctr + ((size_t)(k & 1) * 8 + (size_t)(b & 7)) * kCtrStride;
+  const int dyn0 = tr.first - (b >> 3) + tr.stride;  // lo + Gx
+  int raw = 0;  // lane 0: the counter value of the claim in flight
+  if (claim && lane == 0) raw = atomicAdd(ctr, 1);
   int cache_run = -1;
   unsigned long long n_moved = 0, n_faces = 0;
   uint32_t key0 = 0, key1 = 0, dmask = 0;  // per-run constants (uniform)
@@ -997,8 +1008,9 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   }
   nc = cc;
 
-  for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
-    const bool has_next = tile + tr.stride < tr.end;
+  for (int tile = tr.first, next = 0; tile < tr.end; tile = next) {
+    next = claim ? dyn0 + __builtin_amdgcn_readfirstlane(raw) : tile + tr.stride;
+    const bool has_next = next < tr.end;
     const bool run_active = cc.active;  // else the tile only forwards the prefetch
     const cptr<RunDesc> rd = cc.rd;
     const int T = cc.T;
@@ -1031,9 +1043,10 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
     wave_sync();
     __builtin_amdgcn_sched_barrier(0);
     if (has_next) {
-      nc = tile_ctx(A, tile + tr.stride, k);
+      nc = tile_ctx(A, next, k);
       load_tet<SMAX>(nc, S, nc.base + lane, nxt);
-      nmask = as_const(A.wl_mask)[tile + tr.stride];
+      nmask = as_const(A.wl_mask)[next];
+      if (claim && lane == 0) raw = atomicAdd(ctr, 1);  // the tile after next
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -1537,6 +1550,8 @@ window_main_kernel(const StepArgs A) {
     if (blockIdx.x == 0)  // the next window's queue starts empty
       A.evq_count[(((size_t)((k + 1) & 1) * kBins + bin) * kQueues + lane) * kQueueStride] = 0;
   }
+  if (blockIdx.x == 0 && lane < 8)  // and so do its tile claim counters
+    A.tile_ctr[((size_t)((k + 1) & 1) * 8 + (size_t)lane) * kCtrStride] = 0;
   // event blocks: one per group, a multiple of the 8 XCDs (so that the
   // diffusion blocks keep their XCD mapping), at most half the grid
   int E = 0;

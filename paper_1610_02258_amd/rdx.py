@@ -134,7 +134,7 @@ class _Stats(C.Structure):
 
 class _ExecOptions(C.Structure):
     _fields_ = [("autotune", C.c_int32), ("fast_grid_div", C.c_int32), ("graph_windows", C.c_int32),
-                ("event_group", C.c_int32), ("event_bins", C.c_int32)]
+                ("event_group", C.c_int32), ("event_bins", C.c_int32), ("tile_claim", C.c_int32)]
 
 
 class _ServerOptions(C.Structure):
@@ -367,16 +367,16 @@ class Sim:
         _check(lib().rdx_set_kernel_timing(self._h, int(bool(enable))), "rdx_set_kernel_timing")
 
     def set_exec_options(self, autotune: bool = False, fast_grid_div: int = 1, graph_windows: int = 1,
-                         event_group: int = 0, event_bins: int = 1):
+                         event_group: int = 0, event_bins: int = 1, tile_claim: int = 0):
         o = _ExecOptions(int(bool(autotune)), int(fast_grid_div), int(graph_windows), int(event_group),
-                         int(event_bins))
+                         int(event_bins), int(tile_claim))
         _check(lib().rdx_set_exec_options(self._h, C.byref(o)), "rdx_set_exec_options")
 
     def exec_options(self) -> dict:
         o = _ExecOptions()
         _check(lib().rdx_get_exec_options(self._h, C.byref(o)), "rdx_get_exec_options")
         return dict(autotune=o.autotune, fast_grid_div=o.fast_grid_div, graph_windows=o.graph_windows,
-                    event_group=o.event_group, event_bins=o.event_bins)
+                    event_group=o.event_group, event_bins=o.event_bins, tile_claim=o.tile_claim)
 
     def kernel_times(self, reset: bool = False) -> dict:
         kt = _KernelTimes()
@@ -516,16 +516,16 @@ class Batch:
         return Stats(st.windows, st.voxel_steps, st.ssa_events, st.moves, st.t, st.window_index, st.face_moves)
 
     def set_exec_options(self, autotune: bool = False, fast_grid_div: int = 1, graph_windows: int = 1,
-                         event_group: int = 0, event_bins: int = 1):
+                         event_group: int = 0, event_bins: int = 1, tile_claim: int = 0):
         o = _ExecOptions(int(bool(autotune)), int(fast_grid_div), int(graph_windows), int(event_group),
-                         int(event_bins))
+                         int(event_bins), int(tile_claim))
         _check(lib().rdx_batch_set_exec_options(self._h, C.byref(o)), "rdx_batch_set_exec_options")
 
     def exec_options(self) -> dict:
         o = _ExecOptions()
         _check(lib().rdx_batch_get_exec_options(self._h, C.byref(o)), "rdx_batch_get_exec_options")
         return dict(autotune=o.autotune, fast_grid_div=o.fast_grid_div, graph_windows=o.graph_windows,
-                    event_group=o.event_group, event_bins=o.event_bins)
+                    event_group=o.event_group, event_bins=o.event_bins, tile_claim=o.tile_claim)
 
 
 def _info(ri: _RequestInfo) -> dict:

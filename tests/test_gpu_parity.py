@@ -231,10 +231,14 @@ def test_simple_model_full_size_prefix(rdx, oracle_lib):
         _assert_same(sim, ref, f"window {k}")
 
 
-def test_dendrite_full_size_prefix(rdx, oracle_lib):
+@pytest.mark.parametrize("claim", [0, 1])
+def test_dendrite_full_size_prefix(rdx, oracle_lib, claim):
+    """The dendrite's first windows, diffusion tiles in static ranges and
+    claimed at run time, in graphs of one window."""
     w = I.config_dendrite()
-    _say(f"case: dendrite, T={w.mesh.n_tets}")
+    _say(f"case: dendrite, T={w.mesh.n_tets}, tile claim {claim}")
     sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
+    sim.set_exec_options(autotune=False, fast_grid_div=1, graph_windows=1, event_group=16, tile_claim=claim)
     for k in range(2):
         sim.step(1)
         ref.step(1)
@@ -255,17 +259,19 @@ def test_density_and_refinement_series(rdx, oracle_lib, density, h, extent):
         _assert_same(sim, ref, f"window {k}")
 
 
-@pytest.mark.parametrize("density,h,bins", [(10.0, 0.5, 1), (10.0, 0.5, 0), (1.0, 0.25, 1)])
-def test_series_full_size_prefix(rdx, oracle_lib, density, h, bins):
+@pytest.mark.parametrize("density,h,bins,claim", [(10.0, 0.5, 1, 0), (10.0, 0.5, 0, 0), (10.0, 0.5, 1, 1),
+                                                  (1.0, 0.25, 1, 1)])
+def test_series_full_size_prefix(rdx, oracle_lib, density, h, bins, claim):
     """The series at full size: 480,000 tets with 1e7 molecules (10x the
     benchmarked density, with the listed tets binned by expected events and
-    in one queue) and the refined 3,840,000-tet box (0.25 um cubes): the
-    first windows compared on every count."""
+    in one queue, diffusion tiles in static ranges and claimed at run time)
+    and the refined 3,840,000-tet box (0.25 um cubes): the first windows
+    compared on every count."""
     w = I.config_simple_variant(density, h)
-    _say(f"case: {w.name}, T={w.mesh.n_tets}, event bins {bins}")
+    _say(f"case: {w.name}, T={w.mesh.n_tets}, event bins {bins}, tile claim {claim}")
     sim, ref = _pair(rdx, oracle_lib, w.mesh.as_dict(), w.model.as_dict(), w.seed, w.counts)
     sim.set_exec_options(autotune=False, fast_grid_div=1, graph_windows=1, event_group=8,
-                         event_bins=bins)
+                         event_bins=bins, tile_claim=claim)
     for k in range(2):
         sim.step(1)
         ref.step(1)
