@@ -602,6 +602,19 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
   // the calls of the other items are shared out over the wave
   const bool shared = __ballot(calls > 0u) != 0ull;  // uniform
   if (shared) {
+    // each item's thresholds, made once by its own lane; a lane making one
+    // of its calls reads them across the wave (ds_bpermute, no LDS storage)
+    uint32_t oth0 = 0, oth1 = 0, oth2 = 0, oth3 = 0, ofull = 0;
+    if (calls > 0u) {
+      const double oscale = (info >> 10) & 1u ? 1.0 : item_p(V, it.sp, it.ln);
+      uint32_t th[4], full;
+      item_thresholds(V, it.ln, oscale, th, full);
+      oth0 = th[0];
+      oth1 = th[1];
+      oth2 = th[2];
+      oth3 = th[3];
+      ofull = full;
+    }
     const uint32_t incl = wave_scan_add_dpp(calls);
     const uint32_t first = incl - calls;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
@@ -627,12 +640,18 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
       const int v = X.slot[lane];
       const int item = wave_scan_max_dpp(v > i_lo ? v : i_lo);
       const uint32_t t = b0 + (uint32_t)lane;
+      // read with every lane active: a cross-lane read from a lane that is
+      // switched off returns nothing, and the owner of a call in the last
+      // batch may be a lane past the batch's end
+      uint32_t th[4];
+      th[0] = (uint32_t)__shfl((int)oth0, item, kWave);
+      th[1] = (uint32_t)__shfl((int)oth1, item, kWave);
+      th[2] = (uint32_t)__shfl((int)oth2, item, kWave);
+      th[3] = (uint32_t)__shfl((int)oth3, item, kWave);
+      const uint32_t full = (uint32_t)__shfl((int)ofull, item, kWave);
       if (t < total) {
         const uint32_t iw0 = X.w0[item], inf = X.info[item];
         const int sp = (int)(inf & 15u), ln = (int)((inf >> 4) & 63u);
-        const double scale = (inf >> 10) & 1u ? 1.0 : item_p(V, sp, ln);
-        uint32_t th[4], full;
-        item_thresholds(V, ln, scale, th, full);
         const uint32_t call = (iw0 >> 2) + (t - X.off[item]);
         uint32_t x0 = call, x1 = 1u + (uint32_t)sp, x2 = V.tet_of(ln), x3 = window;
         philox4x32_10(x0, x1, x2, x3, key0, key1);
