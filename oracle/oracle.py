@@ -51,8 +51,6 @@ def _bind(L):
     L.os_philox4x32_10.restype = None
     L.os_ln.argtypes = [C.c_double]
     L.os_ln.restype = C.c_double
-    L.os_sqrt_newton.argtypes = [C.c_double]
-    L.os_sqrt_newton.restype = C.c_double
     L.os_build.argtypes = [C.c_int32, p, C.c_int32, p, p, C.c_int32, C.c_int32, C.c_int32,
                            p, p, p, p, C.c_double, C.POINTER(C.c_void_p)]
     L.os_build.restype = C.c_int
@@ -130,11 +128,6 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 def ln(x: float) -> float:
     return lib().os_ln(float(x))
-
-
-def sqrt_newton(x: float) -> float:
-    """The oracle's reproducible square root (x >= 1), used by the binomial."""
-    return lib().os_sqrt_newton(float(x))
 
 
 def sample_binom(seed: int, m: int, p: float, n: int, stream_id: int = 1, window: int = 0):

@@ -185,117 +185,9 @@ double os_ln(double x)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Square root by Newton's iteration from a power-of-two start (x >= 1):     */
-/* six steps from within a factor two of the root reach double precision.   */
-/* It only has to be reproducible, operation for operation, by the GPU's    */
-/* copy; it is pinned against sqrt to within an ulp.                        */
-/* ------------------------------------------------------------------------ */
-double os_sqrt_newton(double x)
-{
-  uint64_t bits;
-  memcpy(&bits, &x, sizeof bits);
-  int e = (int)((bits >> 52) & 0x7ffu) - 1023;   /* x in [2^e, 2^(e+1)), e >= 0 */
-  uint64_t ybits = (uint64_t)(1023 + e / 2) << 52;
-  double y;
-  memcpy(&y, &ybits, sizeof y);
-  for (int i = 0; i < 6; ++i) y = 0.5 * (y + x / y);
-  return y;
-}
-
-/* Stirling-series remainder of ln k!: ln k! minus                          */
-/* (k + 1/2) ln(k + 1) - (k + 1) + ln sqrt(2 pi); tabulated below 10, else   */
-/* its first three series terms in 1/(k + 1).                                */
-static double os_fc(int64_t k)
-{
-  static const double tab[10] = {
-    0.08106146679532726, 0.0413406959554093, 0.02767792568499834, 0.020790672103765093,
-    0.016644691189821193, 0.013876128823070748, 0.01189670994589177, 0.010411265261972096,
-    0.009255462182712733, 0.00833056343336287 };
-  if (k < 10) return tab[k];
-  double r = 1.0 / (double)(k + 1);
-  double r2 = r * r;
-  return (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0) * r2) * r2) * r;
-}
-
-/* ------------------------------------------------------------------------ */
-/* Binomial variate, n p >= 10 and p <= 1/2: Hormann's transformed          */
-/* rejection with decomposition (BTRD, 1993).  A uniform v below 0.86 v_r   */
-/* maps straight into the centre of the hat; otherwise a second uniform     */
-/* gives a point of the hat, k = floor((2a/us + b) u + c), which is         */
-/* accepted against f(k)/f(mode) -- by the product of successive pmf        */
-/* ratios when |k - mode| <= 15, else by the squeeze of ln(f(k)/f(mode))    */
-/* and, between its bounds, by Stirling's series.  Each attempt draws one   */
-/* or two 32-bit uniforms from the stream; the count is exact in law.       */
-/* ------------------------------------------------------------------------ */
-static int64_t os_btrd(int64_t n, double p, os_stream* st)
-{
-  double q = 1.0 - p;
-  double dn = (double)n;
-  int64_t mo = (int64_t)floor((dn + 1.0) * p); /* the mode */
-  double dmo = (double)mo;
-  double r = p / q;
-  double nr = (dn + 1.0) * r;
-  double npq = (dn * p) * q;
-  double spq = os_sqrt_newton(npq);
-  double b = 1.15 + 2.53 * spq;
-  double a = (-0.0873 + 0.0248 * b) + 0.01 * p;
-  double c = dn * p + 0.5;
-  double alpha = (2.83 + 5.1 / b) * spq;
-  double vr = 0.92 - 4.2 / b;
-  double urvr = 0.86 * vr;
-  for (;;) {
-    double v = os_u32_co(st);
-    double u;
-    if (v <= urvr) {
-      u = v / vr - 0.43;
-      return (int64_t)floor((2.0 * a / (0.5 - fabs(u)) + b) * u + c);
-    }
-    if (v >= vr) {
-      u = os_u32_co(st) - 0.5;
-    } else {
-      u = v / vr - 0.93;
-      u = (u < 0.0 ? -0.5 : 0.5) - u;
-      v = os_u32_co(st) * vr;
-    }
-    double us = 0.5 - fabs(u);
-    if (!(us > 0.0)) continue;
-    double kd = floor((2.0 * a / us + b) * u + c);
-    if (kd < 0.0 || kd > dn) continue;
-    int64_t k = (int64_t)kd;
-    v = v * alpha / (a / (us * us) + b);
-    int64_t km = k > mo ? k - mo : mo - k;
-    if (km <= 15) {
-      /* f(k)/f(mode) as the product of the pmf ratios between them */
-      double f = 1.0;
-      if (mo < k) {
-        for (int64_t i = mo + 1; i <= k; ++i) f = f * (nr / (double)i - r);
-      } else if (mo > k) {
-        for (int64_t i = k + 1; i <= mo; ++i) v = v * (nr / (double)i - r);
-      }
-      if (v <= f) return k;
-      continue;
-    }
-    if (!(v > 0.0)) return k; /* ln v = -inf lies below every bound */
-    v = os_ln(v);
-    double dkm = (double)km;
-    double rho = (dkm / npq) * (((dkm / 3.0 + 0.625) * dkm + 1.0 / 6.0) / npq + 0.5);
-    double t = -(dkm * dkm) / (2.0 * npq);
-    if (v < t - rho) return k;
-    if (v > t + rho) continue;
-    double nm = dn - dmo + 1.0;
-    double h = (dmo + 0.5) * os_ln((dmo + 1.0) / (r * nm)) + os_fc(mo) + os_fc(n - mo);
-    double nk = dn - kd + 1.0;
-    double lim = h + (dn + 1.0) * os_ln(nm / nk) + (kd + 0.5) * os_ln((nk * r) / (kd + 1.0)) - os_fc(k) -
-                 os_fc(n - k);
-    if (v <= lim) return k;
-  }
-}
-
-/* ------------------------------------------------------------------------ */
 /* Binomial variate by sequential-search inversion (one 32-bit uniform per   */
 /* chunk of at most 1000 trials; chunking keeps q^c >= 2^-1000, and a sum    */
-/* of independent Bin(c_i, p) is Bin(sum c_i, p)) where n p < 10, whose      */
-/* searches are short; by BTRD above, whose cost does not grow with n p.     */
+/* of independent Bin(c_i, p) is Bin(sum c_i, p)).                           */
 /* ------------------------------------------------------------------------ */
 static double os_powi(double q, int64_t c)
 {
@@ -311,7 +203,6 @@ static double os_powi(double q, int64_t c)
 static int64_t os_binom_core(int64_t m, double p, os_stream* st)
 {
   /* 0 < p <= 0.5, m > 0 */
-  if ((double)m * p >= 10.0) return os_btrd(m, p, st);
   double q = 1.0 - p;
   double r = p / q;
   int64_t total = 0;
