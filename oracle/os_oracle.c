@@ -213,7 +213,10 @@ static int64_t os_binom_core(int64_t m, double p, os_stream* st)
     double F = f;
     int64_t k = 0;
     while (u >= F && k < c) {
-      f = ((f * r) * (double)(c - k)) / (double)(k + 1);
+      /* the pmf ratio r (c - k) / (k + 1), its division taken as a product
+         with the rounded reciprocal of k + 1 (which the GPU reads from a
+         table instead of dividing at every step) */
+      f = ((f * r) * (double)(c - k)) * (1.0 / (double)(k + 1));
       k = k + 1;
       F = F + f;
     }
