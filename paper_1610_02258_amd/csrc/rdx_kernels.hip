@@ -172,6 +172,19 @@ __device__ __forceinline__ double pow_int(double q, int c) {
   return result;
 }
 
+// Reciprocals 1/(k + 1) for k < 1000 (every step of a chunk's search),
+// rounded once, at compile time, as the division rounds them.  The search's
+// step counter is the same on every lane of a wave (the lanes step together),
+// so the table is read with scalar loads that do not depend on the running
+// pmf value, instead of a double division on the search's dependent chain.
+struct ReciprocalTable {
+  double v[1000];
+  constexpr ReciprocalTable() : v() {
+    for (int k = 0; k < 1000; ++k) v[k] = 1.0 / (double)(k + 1);
+  }
+};
+__constant__ constexpr ReciprocalTable kRecip{};
+
 __device__ long long binom_core(long long m, double p, Draw32& st) {
   const double q = 1.0 - p;
   const double r = p / q;
@@ -183,7 +196,7 @@ __device__ long long binom_core(long long m, double p, Draw32& st) {
     double F = f;
     int k = 0;
     while (u >= F && k < c) {
-      f = ((f * r) * (double)(c - k)) / (double)(k + 1);
+      f = ((f * r) * (double)(c - k)) * kRecip.v[k];
       k = k + 1;
       F = F + f;
     }
