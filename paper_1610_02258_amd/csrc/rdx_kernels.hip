@@ -576,7 +576,10 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
       // draws, so the face counts fit a byte each)
       const int last = last_face(V.nbr[it.ln]);
       const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
-      const double t0 = scale * g0.y, t1 = scale * g1.x, t2 = scale * g1.y;
+      // u = w 2^-32 < t exactly when w < t 2^32 (both scalings are exact), so
+      // the words are compared, as doubles, with the thresholds scaled once
+      const double ts = scale * 0x1p32;
+      const double t0 = (scale * g0.y) * 0x1p32, t1 = (scale * g1.x) * 0x1p32, t2 = (scale * g1.y) * 0x1p32;
       for (uint32_t call = w0 >> 2; call <= (w0 + nw - 1u) >> 2; ++call) {
         uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
         philox4x32_10(x0, x1, x2, x3, key0, key1);
@@ -584,8 +587,8 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         for (int q = 0; q < 4; ++q) {
           const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
           const uint32_t idx = 4u * call + (uint32_t)q;
-          const double u = (double)w * 0x1p-32;
-          if (idx >= w0 && idx - w0 < nw && u < scale) {
+          const double u = (double)w;
+          if (idx >= w0 && idx - w0 < nw && u < ts) {
             const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
             own += 1u << (8 * f);
           }
@@ -715,7 +718,9 @@ __device__ __forceinline__ ItemMoves item_round_small(uint32_t key0, uint32_t ke
     if (p > 0.0) {
       const int last = last_face(V.nbr[it.ln]);
       const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
-      const double t0 = p * g0.y, t1 = p * g1.x, t2 = p * g1.y;
+      // the words against the thresholds scaled by 2^32 (exact, as above)
+      const double ps = p * 0x1p32;
+      const double t0 = (p * g0.y) * 0x1p32, t1 = (p * g1.x) * 0x1p32, t2 = (p * g1.y) * 0x1p32;
       const uint32_t calls = (m + 3u) >> 2;
       for (uint32_t call = 0; call < calls; ++call) {
         uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
@@ -723,8 +728,8 @@ __device__ __forceinline__ ItemMoves item_round_small(uint32_t key0, uint32_t ke
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
-          const double u = (double)w * 0x1p-32;
-          if (4u * call + (uint32_t)q < m && u < p) {
+          const double u = (double)w;
+          if (4u * call + (uint32_t)q < m && u < ps) {
             const int f = (0 < last && u < t0) ? 0 : ((1 < last && u < t1) ? 1 : ((2 < last && u < t2) ? 2 : last));
             own += 1u << (8 * f);
           }
