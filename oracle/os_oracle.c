@@ -685,10 +685,22 @@ static int64_t os_diffuse_leavers(const os_instance* I, int32_t i, int64_t m, do
   }
   n = os_binom(m, p, st);
   if (n > npost) n = npost;
-  for (int64_t j = 0; j < n; ++j) {
-    double u = os_u32_co(st);
-    out[os_pick_face(I, i, u, 1.0)] += 1;
+  /* the n leavers split among the faces in proportion to the face couplings
+     (a multinomial with the shares cum_k - cum_{k-1}), drawn as successive
+     binomials: face k takes Bin(rest, its share of what faces k.. hold), the
+     last face present takes what is left */
+  int last = I->last[i];
+  int64_t rest = n;
+  double prev = 0.0;
+  for (int k = 0; k < last; ++k) {
+    double cum = I->cum[4 * (size_t)i + k];
+    double q = (cum - prev) / (1.0 - prev);
+    int64_t nk = os_binom(rest, q, st);
+    out[k] += nk;
+    rest -= nk;
+    prev = cum;
   }
+  out[last] += rest;
   return n;
 }
 
