@@ -538,7 +538,8 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
   const int lane = threadIdx.x;
   uint32_t w0 = 0, nw = 0, calls = 0, info = 0;
   uint32_t own = 0;     // leavers by face drawn on this lane, a byte each
-  bool walked = false;  // this lane's face counts are in X.face
+  bool walked = false;  // this lane's face counts are in X.face, by the walk
+  bool split = false;   // this lane's face counts are in X.face, by the split
   if (it.valid) {
     const uint32_t tet = V.tet_of(it.ln);
     Draw32 st(key0, key1, 1u + (uint32_t)it.sp, tet, window);
@@ -559,10 +560,33 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         trials = m;
         walked = m > (long long)it.npost;  // the cap may bind mid-walk
       } else {
-        const long long n = binom(m, p, st);
-        if (p < 1.0) used += (uint32_t)((m + 999) / 1000);
-        trials = n > (long long)it.npost ? (long long)it.npost : n;
-        scale = 1.0;
+        // the leaver count, then its split among the faces, one binomial per
+        // stage from one call site, in stream order on this lane: stage 0
+        // draws n = Bin(m, p) (capped at the post-reaction count), stage
+        // k + 1 gives face k Bin(rest, its share of the faces from k on),
+        // and the last face present takes the rest
+        const int last = last_face(V.nbr[it.ln]);
+        const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
+        long long rest = 0;
+        double prev = 0.0;
+#pragma unroll 1
+        for (int stage = 0; stage <= last; ++stage) {
+          const double cum = stage == 1 ? g0.y : (stage == 2 ? g1.x : g1.y);
+          const long long nn = stage == 0 ? m : rest;
+          const double qq = stage == 0 ? p : (cum - prev) / (1.0 - prev);
+          const long long k = binom(nn, qq, st);
+          if (stage == 0) {
+            rest = k > (long long)it.npost ? (long long)it.npost : k;
+          } else {
+            X.face[stage - 1][lane] = (uint32_t)k;
+            rest -= k;
+            prev = cum;
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          if (f >= last) X.face[f][lane] = f == last ? (uint32_t)rest : 0u;
+        split = true;
         binomial = true;
       }
     }
@@ -636,7 +660,7 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (!walked) X.face[k][lane] = 0u;
+      if (!walked && !split) X.face[k][lane] = 0u;
     X.info[lane] = info;
     X.w0[lane] = w0;
     X.nw[lane] = nw;
@@ -693,7 +717,7 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
   if (it.valid) {
     uint32_t o[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = ((own >> (8 * k)) & 0xffu) + (shared || walked ? X.face[k][lane] : 0u);
+    for (int k = 0; k < 4; ++k) o[k] = ((own >> (8 * k)) & 0xffu) + (shared || walked || split ? X.face[k][lane] : 0u);
     r.o0 = (int)o[0];
     r.o1 = (int)o[1];
     r.o2 = (int)o[2];
