@@ -36,10 +36,14 @@
  *     with m <= 16, each of the m molecules draws one 32-bit uniform u and
  *     goes to the first face k (before the last face present) with
  *     u < p cum_k, else to the last face if u < p, else stays; with m > 16,
- *     n = Bin(m, p) by inversion and each leaver draws one uniform for its
- *     face (first k with u < cum_k, else the last face).  cum_k is the
- *     left-to-right prefix sum of the face couplings over G.  Both are exact
- *     samplers of binomial leavers split among neighbours by rate;
+ *     the faces in order take successive binomials (face k: Bin(rest,
+ *     p s_k / (1 - p cum_{k-1})), s_k the face's share) and the rest stay;
+ *     should more leave than the post-reaction count, that many leave, split
+ *     afresh by the shares (successive binomials, the last face present
+ *     taking the rest).  cum_k is the left-to-right prefix sum of the face
+ *     couplings over G.  Both are exact samplers of binomial leavers split
+ *     among neighbours by rate; binomials are drawn by sequential-search
+ *     inversion;
  *   - composition-rejection selection groups reactions by the binary
  *     exponent of their propensity (Slepoy, Thompson & Plimpton 2008);
  *   - random numbers are Philox4x32-10 (Salmon et al., SC'11), keyed by the
@@ -683,24 +687,46 @@ static int64_t os_diffuse_leavers(const os_instance* I, int32_t i, int64_t m, do
     }
     return n;
   }
-  n = os_binom(m, p, st);
-  if (n > npost) n = npost;
-  /* the n leavers split among the faces in proportion to the face couplings
-     (a multinomial with the shares cum_k - cum_{k-1}), drawn as successive
-     binomials: face k takes Bin(rest, its share of what faces k.. hold), the
-     last face present takes what is left */
+  /* each of the m molecules stays (1 - p) or leaves through face k
+     (p s_k, s_k = cum_k - cum_{k-1} the face's share of the couplings): a
+     multinomial over the faces and staying, drawn as successive binomials
+     over the faces: face k takes Bin(rest, p s_k / (1 - p cum_{k-1})) of
+     the molecules not yet placed, and those left over stay.  The number
+     that leave is then Bin(m, p) and, given it, their split among the faces
+     is multinomial with the shares. */
   int last = I->last[i];
-  int64_t rest = n;
+  int64_t f[4] = { 0, 0, 0, 0 };
+  int64_t rest = m;
   double prev = 0.0;
-  for (int k = 0; k < last; ++k) {
-    double cum = I->cum[4 * (size_t)i + k];
-    double q = (cum - prev) / (1.0 - prev);
-    int64_t nk = os_binom(rest, q, st);
-    out[k] += nk;
-    rest -= nk;
+  for (int k = 0; k <= last; ++k) {
+    double cum = k == last ? 1.0 : I->cum[4 * (size_t)i + k];
+    double den = 1.0 - p * prev;
+    /* den is 0 only for p = 1 with the shares before face k summing to 1 */
+    double q = den > 0.0 ? (p * (cum - prev)) / den : (k == last ? 1.0 : 0.0);
+    f[k] = os_binom(rest, q, st);
+    rest -= f[k];
+    n += f[k];
     prev = cum;
   }
-  out[last] += rest;
+  if (n > npost) {
+    /* more leavers than molecules left after the reactions: npost leave,
+       split afresh among the faces by the shares (face k takes Bin(rest,
+       its share of what faces k.. hold), the last face present takes what is
+       left), from the next draws of the stream */
+    n = npost;
+    rest = npost;
+    prev = 0.0;
+    for (int k = 0; k < last; ++k) {
+      double cum = I->cum[4 * (size_t)i + k];
+      double q = (cum - prev) / (1.0 - prev);
+      f[k] = os_binom(rest, q, st);
+      rest -= f[k];
+      prev = cum;
+    }
+    f[last] = rest;
+    for (int k = last + 1; k < 4; ++k) f[k] = 0;
+  }
+  for (int k = 0; k < 4; ++k) out[k] += f[k];
   return n;
 }
 
