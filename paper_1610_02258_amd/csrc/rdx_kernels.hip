@@ -560,32 +560,51 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         trials = m;
         walked = m > (long long)it.npost;  // the cap may bind mid-walk
       } else {
-        // the leaver count, then its split among the faces, one binomial per
-        // stage from one call site, in stream order on this lane: stage 0
-        // draws n = Bin(m, p) (capped at the post-reaction count), stage
-        // k + 1 gives face k Bin(rest, its share of the faces from k on),
-        // and the last face present takes the rest
+        // the multinomial over the faces and staying, one binomial per stage
+        // from one call site, in stream order on this lane: stage k <= last
+        // gives face k Bin(rest, p s_k / (1 - p cum_{k-1})) of the molecules
+        // not yet placed (s_k the face's share, the last face present taking
+        // all that remains of p), the rest stay.  Should more leave than
+        // the post-reaction count (only a listed tet's item can), stages
+        // last + 1 .. 2 last split that count afresh by the shares (face k
+        // Bin(rest, s_k / (1 - cum_{k-1})), the last face the rest).
         const int last = last_face(V.nbr[it.ln]);
         const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
-        long long rest = 0;
+        const long long npost = (long long)it.npost;
+        long long rest = m, n = 0;
         double prev = 0.0;
+        bool capped = false;
+        int end = last;
 #pragma unroll 1
-        for (int stage = 0; stage <= last; ++stage) {
-          const double cum = stage == 1 ? g0.y : (stage == 2 ? g1.x : g1.y);
-          const long long nn = stage == 0 ? m : rest;
-          const double qq = stage == 0 ? p : (cum - prev) / (1.0 - prev);
-          const long long k = binom(nn, qq, st);
-          if (stage == 0) {
-            rest = k > (long long)it.npost ? (long long)it.npost : k;
+        for (int stage = 0; stage <= end; ++stage) {
+          const int f = capped ? stage - last - 1 : stage;
+          const double cum = (!capped && f == last) ? 1.0 : (f == 0 ? g0.y : (f == 1 ? g1.x : g1.y));
+          double qq;
+          if (!capped) {
+            // den is 0 only for p = 1 with the shares before face f summing to 1
+            const double den = 1.0 - p * prev;
+            qq = den > 0.0 ? (p * (cum - prev)) / den : (f == last ? 1.0 : 0.0);
           } else {
-            X.face[stage - 1][lane] = (uint32_t)k;
-            rest -= k;
-            prev = cum;
+            qq = (cum - prev) / (1.0 - prev);
+          }
+          const long long k = binom(rest, qq, st);
+          X.face[f][lane] = (uint32_t)k;
+          rest -= k;
+          prev = cum;
+          if (!capped) {
+            n += k;
+            if (f == last && n > npost) {
+              capped = true;
+              end = last + last;
+              rest = npost;
+              prev = 0.0;
+            }
           }
         }
+        if (capped) X.face[last][lane] = (uint32_t)rest;
 #pragma unroll
         for (int f = 0; f < 4; ++f)
-          if (f >= last) X.face[f][lane] = f == last ? (uint32_t)rest : 0u;
+          if (f > last) X.face[f][lane] = 0u;
         split = true;
         binomial = true;
       }
