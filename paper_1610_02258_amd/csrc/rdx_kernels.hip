@@ -395,22 +395,20 @@ __device__ __forceinline__ int wave_scan_add(int v) {
 // fractional).  With m <= 16 every molecule draws one 32-bit uniform u and
 // leaves when u < p, to the first face k before the last face present with
 // u < p cum_k, else to the last face; once npost molecules have left the
-// rest stay.  With m > 16, n = min(Bin(m, p), npost) leavers each draw one
-// uniform for their face (same rule with p replaced by 1).  Both are exact
-// samplers of binomial leavers split among the faces in proportion to the
-// face couplings.
+// rest stay.  With m > 16 the faces in order take successive binomials of
+// the molecules not yet placed (face k: Bin(rest, p s_k / (1 - p cum_{k-1})),
+// s_k the face's share of the couplings) and the rest stay; should more than
+// npost leave, npost leave instead, split afresh by the shares.  Both are
+// exact samplers of binomial leavers split among the faces in proportion to
+// the face couplings.
 //
-// The face draws of an item are the words w0, w0 + 1, ... of its species
-// stream, w0 the words the rounding and the binomial used; word j is word
-// j mod 4 of Philox call j / 4.  So once w0 and the number of draws are
-// known, any lane can make any of them: a round of up to 64 items is set up
-// one item per lane, then the Philox calls of all its items are shared out
-// over the 64 lanes, each call's words tested against the item's integer
-// thresholds and the face counts summed per item in LDS.  A wave no longer
-// waits on its largest item, and the results are those of the item's own
-// sequential walk, bit for bit.  (With m <= 16 and m > npost the cap can
-// bind in the middle of the walk; such an item -- only a tet whose counts
-// changed in the window can have one -- is walked by its own lane.)
+// The per-molecule draws of an item (m <= 16) are the words w0, w0 + 1, ...
+// of its species stream, w0 the words the rounding used (0 or 1); word j is
+// word j mod 4 of Philox call j / 4, so an item takes at most five calls,
+// which its own lane makes, testing the words against the item's
+// probabilities.  (With m > npost the cap can bind in the middle of the
+// walk; such an item -- only a tet whose counts changed in the window can
+// have one -- is walked word by word in stream order.)
 constexpr int kSmallM = 16;
 
 struct ItemMoves {
@@ -431,14 +429,9 @@ __device__ __forceinline__ int last_face(int4 nb) {
   return nb.w >= 0 ? 3 : (nb.z >= 0 ? 2 : (nb.y >= 0 ? 1 : 0));
 }
 
-// One round's item records and per-item face sums.
+// Per-lane face counts of a round's split and walked items.
 struct ItemLds {
-  uint32_t info[kWave];     // species (bits 0-3), tet lane (bits 4-9), binomial count (bit 10)
-  uint32_t w0[kWave];       // first face draw
-  uint32_t nw[kWave];       // face draws
-  uint32_t off[kWave];      // first call of the item in the round's list of calls
-  uint32_t face[4][kWave];  // leavers by face
-  int8_t slot[kWave];       // item whose calls start at each call of a batch
+  uint32_t face[4][kWave];  // leavers by face of the split and walked items, by lane
 };
 
 // The per-tet arrays a round reads, by tet lane (LDS of the tile or chunk).
@@ -461,35 +454,6 @@ struct ItemIn {
   int npost;   // count after the reactions
 };
 
-// Inclusive prefix over the 64 lanes with DPP row shifts and row
-// broadcasts (no LDS traffic); `old` is the identity of the operation.
-__device__ __forceinline__ uint32_t wave_scan_add_dpp(uint32_t v) {
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-  return v;
-}
-
-__device__ __forceinline__ int wave_scan_max_dpp(int v) {
-  int t;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xf, 0xf, false);
-  v = t > v ? t : v;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xf, 0xf, false);
-  v = t > v ? t : v;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xf, 0xf, false);
-  v = t > v ? t : v;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xf, 0xf, false);
-  v = t > v ? t : v;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xa, 0xf, false);
-  v = t > v ? t : v;
-  t = __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xc, 0xf, false);
-  v = t > v ? t : v;
-  return v;
-}
-
 // Face of a leaving draw w: the number of faces k < last whose threshold w
 // reaches (the thresholds rise with k; faces at or after `last` carry the
 // "never" bit), and whether w leaves at all.
@@ -508,9 +472,9 @@ __device__ __forceinline__ double item_p(const ItemView& V, int sp, int ln) {
   return pr > 1.0 ? 1.0 : pr;
 }
 
-// Integer thresholds of an item's face draws (scale = p, or 1 after a
-// binomial count); `full` bit k: threshold k is never reached (k at or
-// after the last face) or always (2^32), bit 3: every draw leaves.
+// Integer thresholds of an item's face draws (scale = p); `full` bit k:
+// threshold k is never reached (k at or after the last face) or always
+// (2^32), bit 3: every draw leaves.
 __device__ __forceinline__ void item_thresholds(const ItemView& V, int ln, double scale, uint32_t th[4],
                                                 uint32_t& full) {
   const int last = last_face(V.nbr[ln]);
@@ -523,20 +487,9 @@ __device__ __forceinline__ void item_thresholds(const ItemView& V, int ln, doubl
   full = (f0 || last <= 0 ? 1u : 0u) | (f1 || last <= 1 ? 2u : 0u) | (f2 || last <= 2 ? 4u : 0u) | (fs ? 8u : 0u);
 }
 
-// An item with more face draws than this is walked by its own lane, which
-// keeps a round's calls within 32 bits (only counts of hundreds of millions
-// come near it).
-constexpr uint32_t kMaxSharedCalls = 1u << 24;
-
-// An item with at most this many Philox calls makes them on its own lane;
-// only longer ones (a few species with hundreds of molecules per tet) are
-// shared out, where a lane's walk would hold up the wave.
-constexpr uint32_t kOwnCalls = 4u;
-
 __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, const ItemIn& it,
                                 const ItemView& V, ItemLds& X) {
   const int lane = threadIdx.x;
-  uint32_t w0 = 0, nw = 0, calls = 0, info = 0;
   uint32_t own = 0;     // leavers by face drawn on this lane, a byte each
   bool walked = false;  // this lane's face counts are in X.face, by the walk
   bool split = false;   // this lane's face counts are in X.face, by the split
@@ -552,9 +505,7 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
       used = 1;
     }
     const double p = item_p(V, it.sp, it.ln);
-    double scale = p;
     long long trials = 0;
-    bool binomial = false;
     if (m > 0 && p > 0.0) {
       if (m <= kSmallM) {
         trials = m;
@@ -606,23 +557,19 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
         for (int f = 0; f < 4; ++f)
           if (f > last) X.face[f][lane] = 0u;
         split = true;
-        binomial = true;
       }
     }
-    w0 = used;
-    nw = (uint32_t)trials;
-    if (nw > 0u) calls = ((w0 + nw - 1u) >> 2) - (w0 >> 2) + 1u;
-    if (calls > kMaxSharedCalls) walked = true;
-    if (calls >= 1u && calls <= kOwnCalls && !walked) {
-      // few Philox calls: this lane makes them, comparing each uniform
-      // w 2^-32 with the item's probabilities as they are (at most 16
-      // draws, so the face counts fit a byte each)
+    const uint32_t w0 = used, nw = (uint32_t)trials;
+    if (nw > 0u && !walked) {
+      // at most five Philox calls (16 draws after the rounding draw): this
+      // lane makes them, comparing each uniform w 2^-32 with the item's
+      // probabilities as they are (the face counts fit a byte each)
       const int last = last_face(V.nbr[it.ln]);
       const double2 g0 = V.geo0[it.ln], g1 = V.geo1[it.ln];
       // u = w 2^-32 < t exactly when w < t 2^32 (both scalings are exact), so
       // the words are compared, as doubles, with the thresholds scaled once
-      const double ts = scale * 0x1p32;
-      const double t0 = (scale * g0.y) * 0x1p32, t1 = (scale * g1.x) * 0x1p32, t2 = (scale * g1.y) * 0x1p32;
+      const double ts = p * 0x1p32;
+      const double t0 = (p * g0.y) * 0x1p32, t1 = (p * g1.x) * 0x1p32, t2 = (p * g1.y) * 0x1p32;
       for (uint32_t call = w0 >> 2; call <= (w0 + nw - 1u) >> 2; ++call) {
         uint32_t x0 = call, x1 = 1u + (uint32_t)it.sp, x2 = tet, x3 = window;
         philox4x32_10(x0, x1, x2, x3, key0, key1);
@@ -637,12 +584,10 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
           }
         }
       }
-      calls = 0u;
-      nw = 0u;
     }
-    if (walked) {  // in stream order, after the rounding draw and the binomial
+    if (walked) {  // in stream order, after the rounding draw
       uint32_t th[4], full;
-      item_thresholds(V, it.ln, scale, th, full);
+      item_thresholds(V, it.ln, p, th, full);
 #pragma unroll
       for (int k = 0; k < 4; ++k) X.face[k][lane] = 0u;
       long long n = 0;
@@ -653,90 +598,13 @@ __device__ ItemMoves item_round(uint32_t key0, uint32_t key1, uint32_t window, c
           ++n;
         }
       }
-      calls = 0u;
-      nw = 0u;
-    }
-    info = (uint32_t)it.sp | ((uint32_t)it.ln << 4) | (binomial ? 1u << 10 : 0u);
-  }
-  // the calls of the other items are shared out over the wave
-  const bool shared = __ballot(calls > 0u) != 0ull;  // uniform
-  if (shared) {
-    // each item's thresholds, made once by its own lane; a lane making one
-    // of its calls reads them across the wave (ds_bpermute, no LDS storage)
-    uint32_t oth0 = 0, oth1 = 0, oth2 = 0, oth3 = 0, ofull = 0;
-    if (calls > 0u) {
-      const double oscale = (info >> 10) & 1u ? 1.0 : item_p(V, it.sp, it.ln);
-      uint32_t th[4], full;
-      item_thresholds(V, it.ln, oscale, th, full);
-      oth0 = th[0];
-      oth1 = th[1];
-      oth2 = th[2];
-      oth3 = th[3];
-      ofull = full;
-    }
-    const uint32_t incl = wave_scan_add_dpp(calls);
-    const uint32_t first = incl - calls;
-    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (!walked && !split) X.face[k][lane] = 0u;
-    X.info[lane] = info;
-    X.w0[lane] = w0;
-    X.nw[lane] = nw;
-    X.off[lane] = first;
-    wave_sync();
-    // batches of 64 calls: the item holding call b0 is the last lane with
-    // calls whose first call is at most b0; the items starting inside the
-    // batch mark their first call, and a running maximum over the lanes
-    // carries each mark to the calls after it
-    for (uint32_t b0 = 0; b0 < total; b0 += kWave) {
-      const unsigned long long held = __ballot(calls > 0u && first <= b0);
-      const int i_lo = 63 - __builtin_clzll(held);
-      X.slot[lane] = -1;
-      wave_sync();
-      if (calls > 0u && first > b0 && first - b0 < (uint32_t)kWave) X.slot[first - b0] = (int8_t)lane;
-      wave_sync();
-      const int v = X.slot[lane];
-      const int item = wave_scan_max_dpp(v > i_lo ? v : i_lo);
-      const uint32_t t = b0 + (uint32_t)lane;
-      // read with every lane active: a cross-lane read from a lane that is
-      // switched off returns nothing, and the owner of a call in the last
-      // batch may be a lane past the batch's end
-      uint32_t th[4];
-      th[0] = (uint32_t)__shfl((int)oth0, item, kWave);
-      th[1] = (uint32_t)__shfl((int)oth1, item, kWave);
-      th[2] = (uint32_t)__shfl((int)oth2, item, kWave);
-      th[3] = (uint32_t)__shfl((int)oth3, item, kWave);
-      const uint32_t full = (uint32_t)__shfl((int)ofull, item, kWave);
-      if (t < total) {
-        const uint32_t iw0 = X.w0[item], inf = X.info[item];
-        const int sp = (int)(inf & 15u), ln = (int)((inf >> 4) & 63u);
-        const uint32_t call = (iw0 >> 2) + (t - X.off[item]);
-        uint32_t x0 = call, x1 = 1u + (uint32_t)sp, x2 = V.tet_of(ln), x3 = window;
-        philox4x32_10(x0, x1, x2, x3, key0, key1);
-        const uint32_t inw = X.nw[item];
-        uint32_t packed = 0;  // leavers of this call by face, a byte each
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t w = q == 0 ? x0 : (q == 1 ? x1 : (q == 2 ? x2 : x3));
-          const uint32_t idx = 4u * call + (uint32_t)q;
-          if (idx >= iw0 && idx - iw0 < inw && draw_leaves(w, th[3], full))
-            packed += 1u << (8 * draw_face(w, th[0], th[1], th[2], full));
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t c = (packed >> (8 * k)) & 0xffu;
-          if (c) atomicAdd(&X.face[k][item], c);
-        }
-      }
-      wave_sync();  // the slots are rebuilt for the next batch
     }
   }
   ItemMoves r{0, 0, 0, 0, 0};
   if (it.valid) {
     uint32_t o[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = ((own >> (8 * k)) & 0xffu) + (shared || walked || split ? X.face[k][lane] : 0u);
+    for (int k = 0; k < 4; ++k) o[k] = ((own >> (8 * k)) & 0xffu) + (walked || split ? X.face[k][lane] : 0u);
     r.o0 = (int)o[0];
     r.o1 = (int)o[1];
     r.o2 = (int)o[2];
@@ -1144,7 +1012,7 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
           if (((dmask >> s) & 1u) && n_own[s] > 0) mask |= 1u << s;
       }
       // items in three classes, each species-major: more than 16 molecules
-      // (a binomial count each), so that few rounds wait on a binomial; then
+      // (binomial face counts), so that few rounds wait on a binomial; then
       // 5 to 16 (two to four Philox calls on the item's lane); then 1 to 4
       // (one call).  A round's lanes step through as many calls as its
       // longest item has, so grouping items by their number of calls keeps
