@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_1610_02258_amd import inputs as I
-from tests.meshes import mirror_pair, model, single_tet
+from tests.meshes import mirror_pair, model, single_tet, stars
 from tests.randmodels import random_counts, random_model
 
 pytestmark = pytest.mark.gpu
@@ -182,6 +182,30 @@ def test_edge_cases(rdx, oracle_lib):
     # run to a time already reached is a no-op
     sim.run(sim.stats().t)
     assert sim.stats().windows == 3
+
+
+@pytest.mark.parametrize("p_centre", [0.9, 1.0])
+def test_binomial_items_where_the_cap_binds(rdx, oracle_lib, p_centre):
+    """Listed centres whose binomial items would lose more molecules than the
+    reactions left (A -> 0 in the centre at k tau = 0.2, 60 molecules, p = 0.9
+    or 1): the branch that splits the post-reaction count afresh, bit for bit
+    against the oracle, then two more windows with every tet in play."""
+    n_st, N0, D = 2000, 60, 1e-12
+    G = oracle_lib.Instance(stars(1), model([D], [(["A"], [], 1.0)], ["A"]), 1).geometry()["G"][0]
+    tau = (p_centre if p_centre < 1.0 else 1.5) / (D * G)
+    md = model([D], [(["A"], [], 0.2 / tau)], ["A"])
+    c = np.zeros((1, 5 * n_st), np.int32)
+    c[0, 0::5] = N0
+    _say(f"capped binomial items, p {p_centre}, {5 * n_st} tets")
+    sim, ref = _pair(rdx, oracle_lib, stars(n_st), md, 31, c, tau=tau)
+    sim.step(1)
+    ref.step(1)
+    _assert_same(sim, ref, f"p {p_centre}, window 1")
+    # the centres the cap emptied (all of them at p = 1)
+    assert (ref.counts[0, 0::5] == 0).mean() > 0.2
+    sim.step(2)
+    ref.step(2)
+    _assert_same(sim, ref, f"p {p_centre}, windows 2-3")
 
 
 def test_checkpoint_resume_is_bit_identical(rdx, oracle_lib):
