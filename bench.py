@@ -544,6 +544,7 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
         w = inputs.config_simple_variant(density, h)
         print(f"bench: sweep {w.name}", file=sys.stderr, flush=True)
         sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
+        sim.set_exec_options(autotune=True)
         t_end = windows * sim.tau
         c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to(dev)
 
@@ -551,8 +552,15 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
             sim.set_counts(c0, stream=stream)
             sim.run(t_end, stream=stream)
 
-        run()
-        torch.cuda.synchronize()
+        # warm up until the online tuner has settled (it scores every
+        # candidate shape twice, about 300 windows), so that the timed runs
+        # and the per-kernel pass run the shape it picks
+        for k in range(8):
+            run()
+            torch.cuda.synchronize()
+            if k >= 1 and not sim.exec_options()["autotune"]:
+                break
+        shape = sim.exec_options()
         t0 = time.perf_counter()
         for _ in range(steps):
             run()
@@ -579,7 +587,8 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
                      "window_us": el * 1e6 / (st.windows * steps),
                      "main_us": main_s * 1e6, "detect_us": det_s * 1e6,
                      "main_frac_of_hbm": b_main / main_s / 1e9 / HBM_PEAK_GBS,
-                     "detect_frac_of_hbm": b_det / det_s / 1e9 / HBM_PEAK_GBS})
+                     "detect_frac_of_hbm": b_det / det_s / 1e9 / HBM_PEAK_GBS,
+                     "launch_shape": shape})
         sim.close()
         del c0
     return rows
