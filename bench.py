@@ -48,6 +48,14 @@ TRACES = {
     "dendrite_calcium15": os.path.join(ROOT, "profiles", "window_kernels_dendrite_kernel_trace.txt"),
     "box20x20x200_simple10": os.path.join(ROOT, "profiles", "window_kernels_simple10_kernel_trace.txt"),
 }
+SQ_COUNTERS = {
+    "dendrite_calcium15": os.path.join(ROOT, "profiles", "window_kernels_dendrite_sq_counters.txt"),
+    "box20x20x200_simple10": os.path.join(ROOT, "profiles", "window_kernels_simple10_sq_counters.txt"),
+}
+# VALU issue peak in wave64 instructions per second: 256 CUs x 4 SIMDs at
+# 2.4 GHz, one wave64 instruction per SIMD every 4 cycles (times 64 lanes and
+# 2 flops per FMA this is the published 78.6 TFLOP/s of fp64 vector work)
+VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def window_bytes(T: int, S: int, face_moves: float) -> float:
@@ -85,6 +93,17 @@ def measured_traffic(workload: str = "dendrite_calcium15"):
         fetch = float(kv["FETCH_SIZE_KiB_per_dispatch"]) * float(kv["fetch_factor"])
         write = float(kv["WRITE_SIZE_KiB_per_dispatch"]) * float(kv["write_factor"])
         return (fetch + write) * 1024.0
+    except (TypeError, KeyError, ValueError):
+        return None
+
+
+def measured_valu(workload: str = "dendrite_calcium15"):
+    """VALU wave instructions per launch of the main kernel from the
+    committed rocprofv3 SQ counter summary (SQ_INSTS_VALU), or None if the
+    kernel source changed since."""
+    kv = _summary(SQ_COUNTERS[workload])
+    try:
+        return float(kv["window_main_kernel_SQ_INSTS_VALU_per_dispatch"])
     except (TypeError, KeyError, ValueError):
         return None
 
@@ -197,6 +216,11 @@ def roofline(T: int, S: int, n_regions: int, windows: int, face_moves: int, kt: 
     if rp:
         out["rocprof"] = {"main_us": rp["main_us"], "detect_us": rp["detect_us"],
                           "frac_main": b / (rp["main_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    v = measured_valu(workload)
+    if v:  # the issue side: counted VALU instructions over the same duration
+        out["valu_issue"] = {"instructions_per_launch": v, "achieved_per_s": v / main_s,
+                             "peak_per_s": VALU_PEAK_PER_S, "frac": v / main_s / VALU_PEAK_PER_S,
+                             "unit": "wave64 VALU instructions/s", "source": "rocprofv3 SQ_INSTS_VALU"}
     return out
 
 

@@ -63,3 +63,27 @@ def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     src.write_bytes(b"kernel text, changed")
     assert bench.measured_traffic("w") is None
 
+
+
+def test_valu_issue_only_for_the_profiled_source(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel text")
+    sha = hashlib.sha256(b"kernel text").hexdigest()
+    summary = tmp_path / "sq.txt"
+    summary.write_text("# window_main_kernel<16, 24>  2856  1.0  2.0\n"
+                       "window_main_kernel<16, 24>        2856   349872576.4\n"
+                       f"kernel_source_sha256: {sha}\n"
+                       "window_main_kernel_SQ_INSTS_VALU_per_dispatch: 614400\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "SQ_COUNTERS", {"dendrite_calcium15": str(summary)})
+    monkeypatch.setattr(bench, "TRACES", {"dendrite_calcium15": str(tmp_path / "none.txt")})
+    monkeypatch.setattr(bench, "COUNTERS", {"dendrite_calcium15": str(tmp_path / "none.txt")})
+    assert bench.measured_valu() == 614400.0
+    # 1024 SIMDs x 2.4 GHz / 4 cycles: 614.4e9 wave64 instructions per second
+    assert bench.VALU_PEAK_PER_S == pytest.approx(614.4e9)
+    kt = {"windows": 1, "main_ms": 1e-3, "detect_ms": 1e-3}  # 1 us per launch
+    r = bench.roofline(1000, 15, 2, 1, 0, kt, "test", "dendrite_calcium15")
+    assert r["valu_issue"]["frac"] == pytest.approx(614400 / 1e-6 / 614.4e9)
+    src.write_bytes(b"kernel text, changed")
+    assert bench.measured_valu() is None
+    assert "valu_issue" not in bench.roofline(1000, 15, 2, 1, 0, kt, "test", "dendrite_calcium15")
