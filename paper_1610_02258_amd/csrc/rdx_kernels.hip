@@ -924,9 +924,12 @@ union MainLds {
 };
 
 // Diffusion blocks (b of G): the tets not listed, tile by tile, persistent,
-// the next tile's loads in flight while the current one is worked on.
+// the next tile's loads in flight while the current one is worked on.  With
+// `claim_only` (an event block done with its groups, b its XCD) the block has
+// no static tile and takes only claimed ones.
 template <int SMAX, int RMAX>
-__device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, int G, DiffusionLds<SMAX>& L) {
+__device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, int G, DiffusionLds<SMAX>& L,
+                                               bool claim_only) {
   const int lane = threadIdx.x;
   const int S = A.S;
   const int n_tiles = *as_const(A.n_tiles);
@@ -940,6 +943,12 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   const bool claim = A.tile_claim != 0 && G >= 8 && n_tiles >= 8;
   int32_t* const ctr = A.tile_ctr + ((size_t)(k & 1) * 8 + (size_t)(b & 7)) * kCtrStride;
   const int dyn0 = tr.first - (b >> 3) + tr.stride;  // lo + Gx
+  int first = tr.first;
+  if (claim_only) {
+    int r0 = 0;
+    if (lane == 0) r0 = atomicAdd(ctr, 1);
+    first = dyn0 + __builtin_amdgcn_readfirstlane(r0);
+  }
   int raw = 0;  // lane 0: the counter value of the claim in flight
   if (claim && lane == 0) raw = atomicAdd(ctr, 1);
   int cache_run = -1;
@@ -949,14 +958,14 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   TileCtx cc, nc;
   TetData<SMAX> cur, nxt;
   unsigned long long cmask = 0, nmask = 0;  // listed tets of the tile
-  if (tr.first < tr.end) {
-    cc = tile_ctx(A, tr.first, k);
+  if (first < tr.end) {
+    cc = tile_ctx(A, first, k);
     load_tet<SMAX>(cc, S, cc.base + lane, cur);
-    cmask = as_const(A.wl_mask)[tr.first];
+    cmask = as_const(A.wl_mask)[first];
   }
   nc = cc;
 
-  for (int tile = tr.first, next = 0; tile < tr.end; tile = next) {
+  for (int tile = first, next = 0; tile < tr.end; tile = next) {
     next = claim ? dyn0 + __builtin_amdgcn_readfirstlane(raw) : tile + tr.stride;
     const bool has_next = next < tr.end;
     const bool run_active = cc.active;  // else the tile only forwards the prefetch
@@ -1508,8 +1517,18 @@ window_main_kernel(const StepArgs A) {
     E = (n_groups + 7) & ~7;
     if (E > cap) E = cap;
   }
-  if ((int)blockIdx.x < E) event_part<SMAX, RMAX>(A, k, blockIdx.x, E, Q, lds.e);
-  else diffusion_part<SMAX, RMAX>(A, k, (int)blockIdx.x - E, G - E, lds.d);
+  // with tiles claimed at run time an event block done with its groups
+  // takes diffusion tiles of its XCD (E is a multiple of 8, so block b is on
+  // the XCD of diffusion block b - E)
+  const int GD = G - E;
+  const bool join = A.tile_claim != 0 && GD >= 8 && *as_const(A.n_tiles) >= 8;
+  const bool ev = (int)blockIdx.x < E;
+  if (ev) {
+    event_part<SMAX, RMAX>(A, k, blockIdx.x, E, Q, lds.e);
+    if (!join) return;
+    wave_sync();  // the event layout's last reads are done before the diffusion layout is written
+  }
+  diffusion_part<SMAX, RMAX>(A, k, ev ? (int)(blockIdx.x & 7u) : (int)blockIdx.x - E, GD, lds.d, ev);
 }
 
 __global__ void advance_base_kernel(int32_t* base, int32_t add) { *base += add; }
