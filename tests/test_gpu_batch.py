@@ -63,6 +63,8 @@ def _assert_run(b, i, ref, what):
 @pytest.mark.parametrize("shape", [dict(fast_grid_div=1, graph_windows=1, event_group=1),
                                    dict(fast_grid_div=2, graph_windows=4),
                                    dict(fast_grid_div=4, graph_windows=8, event_group=8),
+                                   # tiles claimed at run time, event blocks joining the claims
+                                   dict(fast_grid_div=1, graph_windows=4, event_group=4, tile_claim=1),
                                    dict(autotune=True)])
 def test_batch_matches_oracle_runs(rdx, oracle_lib, shape):
     runs = _small_ensemble()
