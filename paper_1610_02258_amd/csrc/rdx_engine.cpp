@@ -272,7 +272,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
             dev_alloc(&wl_tile_count_, (size_t)max_tiles_) == hipSuccess && dev_alloc(&wl_mask_, (size_t)max_tiles_) == hipSuccess &&
             dev_alloc(&evq_, (size_t)kBins * kQueues * (size_t)((max_tiles_ + kQueues - 1) / kQueues)) == hipSuccess &&
             dev_alloc(&evq_count_, (size_t)2 * kBins * kQueues * kQueueStride) == hipSuccess &&
-            dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&tile_ctr_, (size_t)2 * 8 * kCtrStride) == hipSuccess;
+            dev_alloc(&wl_tet_, W) == hipSuccess && dev_alloc(&tile_ctr_, (size_t)2 * 8 * kClaimSubs * kCtrStride) == hipSuccess;
   if (ok && arena_bytes) ok = arena_.reserve(arena_bytes) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_runs_), sizeof(RunDesc) * (size_t)max_runs) == hipSuccess;
   if (ok) ok = hipHostMalloc(reinterpret_cast<void**>(&h_tile_map_), sizeof(int2) * (size_t)max_tiles_) == hipSuccess;
@@ -290,7 +290,7 @@ rdx_status Engine::init(const HostInstance& proto, size_t arena_bytes, int max_r
   RDX_HIP(hipMemsetAsync(d_base_, 0, sizeof(int32_t), own_));
   RDX_HIP(hipMemsetAsync(wl_tile_count_, 0, sizeof(int32_t) * (size_t)max_tiles_, own_));
   RDX_HIP(hipMemsetAsync(evq_count_, 0, sizeof(unsigned long long) * 2 * kBins * kQueues * kQueueStride, own_));
-  RDX_HIP(hipMemsetAsync(tile_ctr_, 0, sizeof(int32_t) * 2 * 8 * kCtrStride, own_));
+  RDX_HIP(hipMemsetAsync(tile_ctr_, 0, sizeof(int32_t) * 2 * 8 * kClaimSubs * kCtrStride, own_));
   RDX_HIP(hipStreamSynchronize(own_));
   return RDX_OK;
 }

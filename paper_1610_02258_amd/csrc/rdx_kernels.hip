@@ -936,18 +936,29 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   const TileRange tr = tile_range(b, G, n_tiles);
   // Run-time claiming (a launch-shape setting, for workloads whose tiles
   // differ in cost): the block's first tile is its static one, lo + j; the
-  // tiles from lo + Gx on are handed out in order by its XCD's counter, each
-  // claim issued one tile ahead so that its latency hides behind a tile's
-  // work.  A block stops at its first claim past the range, so every block
-  // ends, and the slowest finishes within about one tile of the others.
+  // tiles from lo + Gx on are cut into kClaimSubs sub-ranges (fewer if the
+  // XCD has fewer blocks), each handed out in order by a counter of its own
+  // to the blocks with j mod kClaimSubs equal to its index, each claim
+  // issued one tile ahead so that its latency hides behind a tile's work.
+  // Eight counters per XCD keep the claims at a window's start from queueing
+  // on one address.  A block stops at its first claim past its sub-range,
+  // so every block ends, and the slowest finishes within about one tile of
+  // the others.
   const bool claim = A.tile_claim != 0 && G >= 8 && n_tiles >= 8;
-  int32_t* const ctr = A.tile_ctr + ((size_t)(k & 1) * 8 + (size_t)(b & 7)) * kCtrStride;
   const int dyn0 = tr.first - (b >> 3) + tr.stride;  // lo + Gx
+  const int nsub = tr.stride < kClaimSubs ? (tr.stride > 0 ? tr.stride : 1) : kClaimSubs;
+  const int sub = (claim_only ? (int)(blockIdx.x >> 3) : (b >> 3)) % nsub;
+  int32_t* const ctr =
+      A.tile_ctr + ((size_t)(k & 1) * 8 * kClaimSubs + (size_t)(b & 7) * kClaimSubs + (size_t)sub) * kCtrStride;
+  const int n_claim = tr.end > dyn0 ? tr.end - dyn0 : 0;
+  const int sub_lo = dyn0 + (int)(((long long)n_claim * sub) / nsub);
+  const int sub_hi = dyn0 + (int)(((long long)n_claim * (sub + 1)) / nsub);
   int first = tr.first;
   if (claim_only) {
     int r0 = 0;
     if (lane == 0) r0 = atomicAdd(ctr, 1);
-    first = dyn0 + __builtin_amdgcn_readfirstlane(r0);
+    const int c0 = __builtin_amdgcn_readfirstlane(r0);
+    first = sub_lo + c0 < sub_hi ? sub_lo + c0 : tr.end;
   }
   int raw = 0;  // lane 0: the counter value of the claim in flight
   if (claim && lane == 0) raw = atomicAdd(ctr, 1);
@@ -966,7 +977,12 @@ __device__ __forceinline__ void diffusion_part(const StepArgs& A, int k, int b, 
   nc = cc;
 
   for (int tile = first, next = 0; tile < tr.end; tile = next) {
-    next = claim ? dyn0 + __builtin_amdgcn_readfirstlane(raw) : tile + tr.stride;
+    if (claim) {
+      const int c = __builtin_amdgcn_readfirstlane(raw);
+      next = sub_lo + c < sub_hi ? sub_lo + c : tr.end;
+    } else {
+      next = tile + tr.stride;
+    }
     const bool has_next = next < tr.end;
     const bool run_active = cc.active;  // else the tile only forwards the prefetch
     const cptr<RunDesc> rd = cc.rd;
@@ -1507,8 +1523,8 @@ window_main_kernel(const StepArgs A) {
     if (blockIdx.x == 0)  // the next window's queue starts empty
       A.evq_count[(((size_t)((k + 1) & 1) * kBins + bin) * kQueues + lane) * kQueueStride] = 0;
   }
-  if (blockIdx.x == 0 && lane < 8)  // and so do its tile claim counters
-    A.tile_ctr[((size_t)((k + 1) & 1) * 8 + (size_t)lane) * kCtrStride] = 0;
+  if (blockIdx.x == 0 && lane < 8 * kClaimSubs)  // and so do its tile claim counters
+    A.tile_ctr[((size_t)((k + 1) & 1) * 8 * kClaimSubs + (size_t)lane) * kCtrStride] = 0;
   // event blocks: one per group, a multiple of the 8 XCDs (so that the
   // diffusion blocks keep their XCD mapping), at most half the grid
   int E = 0;

@@ -90,13 +90,15 @@ struct StepArgs {
                                   // counter: queued tiles (low word), their listed tets (high word)
   int32_t* wl_tet;
   // diffusion tiles claimed at run time: after its first (static) tile, a
-  // diffusion block takes the next unclaimed tile of its XCD's range from
-  // tile_ctr[(k & 1) * 8 + xcd] (one 128-byte line each); 0: static ranges
+  // diffusion block takes the next unclaimed tile of its sub-range of its
+  // XCD's range from tile_ctr[(k & 1)][xcd][sub] (one 128-byte line each);
+  // 0: static ranges
   int32_t tile_claim;
-  int32_t* tile_ctr;           // [2][8][kCtrStride] by step parity
+  int32_t* tile_ctr;           // [2][8][kClaimSubs][kCtrStride] by step parity
 };
 
 constexpr int kCtrStride = 32;  // int32 per claim counter line
+constexpr int kClaimSubs = 8;   // claim counters (sub-ranges) per XCD range
 
 constexpr int kQueues = 64;
 constexpr int kBins = 2;  // heavy, light
