@@ -420,7 +420,7 @@ def batched_leg(steps: int = 2) -> dict:
 
     # warm-up, which also runs the online tuning of the launch shape (its
     # candidate shapes are timed on real windows; a step may not hold them all)
-    for _ in range(12):
+    for _ in range(20):
         batch_step()
         torch.cuda.synchronize()
         if not b.exec_options()["autotune"]:
@@ -577,7 +577,7 @@ def sweep_leg(steps: int, windows: int = 200) -> list:
             sim.run(t_end, stream=stream)
 
         # warm up until the online tuner has settled (it scores every
-        # candidate shape twice, about 300 windows), so that the timed runs
+        # candidate shape three times, about 440 windows), so that the timed runs
         # and the per-kernel pass run the shape it picks
         for k in range(8):
             run()

@@ -223,7 +223,7 @@ def test_batch_options_validation(rdx):
     assert b.exec_options()["event_group"] == 2 and b.exec_options()["event_bins"] == 0
     # the tuner's choice is one of its candidates and is kept once tuning ends
     b.set_exec_options(autotune=True)
-    b.step(400)  # enough windows for every candidate
+    b.step(600)  # enough windows for every candidate, three passes
     o = b.exec_options()
     assert o["autotune"] == 0 and o["event_group"] in (4, 8, 16, 64) and o["fast_grid_div"] in (1, 2, 4)
 
@@ -278,7 +278,7 @@ def test_ensemble_as_benchmarked_sampled(rdx, oracle_lib):
     c0 = [torch.from_numpy(np.ascontiguousarray(w.counts)).to("cuda:0") for w in runs]
     stream = torch.cuda.current_stream()
     t_end = [w.t_end for w in runs]
-    for _ in range(12):  # as the benchmark's warm-up: until the tuner has settled
+    for _ in range(20):  # as the benchmark's warm-up: until the tuner has settled
         b.set_counts_all(c0, stream=stream)
         b.run(t_end, stream=stream)
         torch.cuda.synchronize()

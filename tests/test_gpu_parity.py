@@ -313,9 +313,11 @@ def test_simple_model_whole_benchmarked_run(rdx, oracle_lib):
     sim = rdx.Sim(w.mesh.as_dict(), w.model.as_dict(), w.seed)
     c0 = torch.from_numpy(np.ascontiguousarray(w.counts)).to("cuda:0")
     stream = torch.cuda.current_stream()
-    for _ in range(2):  # the first run also tunes the launch shape
+    for k in range(6):  # the first runs also tune the launch shape
         sim.set_counts(c0, stream=stream)
         sim.run(w.t_end, stream=stream)
+        if k >= 1 and not sim.exec_options()["autotune"]:
+            break
     assert sim.exec_options()["autotune"] == 0
     ref = oracle_lib.Instance(w.mesh.as_dict(), w.model.as_dict(), w.seed)
     ref.reset(w.counts)
